@@ -1,0 +1,254 @@
+"""Throughput of the cascaded D2Q9 LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Headline (`value`): MLUPS of the plain FP32 step on the lid-driven cavity
+4096 x 4096 (Re 1000, lid 0.1, tau 1.7288; seeded density noise 1e-6), with
+the lattices resident in HBM: W untimed steps, then exactly K steps timed with
+HIP events on the library's stream.  One JSON line on stdout, also carrying:
+  roofline      the step kernel's algorithmic bytes (72 B per node for FP32:
+                nine 4-byte loads and nine 4-byte stores) over its measured
+                average duration, against MI355X's 8 TB/s;
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cavity;
+  forms         FP16/BF16 deviation storage on Taylor-Green 8192 x 8192
+                (MLUPS, roofline at 36 B per node) with their velocity and
+                strain-rate error against the FP64 path on Taylor-Green
+                512 x 512 after 20k steps; forward + adjoint rollout MLUPS on
+                512 x 512 FP32 (T = 2000, checkpoint every 100) with the FP32
+                gradient's relative error against the FP64 gradient.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}
+METRIC = "MLUPS + % HBM peak, FP32 vs FP16-storage; fwd+adjoint MLUPS at fixed error"
+STEP_SOURCES = ["paper_1202_6351_amd/csrc/lbm_kernels.hip", "paper_1202_6351_amd/csrc/cascade.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fp32_cavity4096.txt")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in STEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 step from the committed counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"kernel_source_sha256:\s*(\w+)", txt)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m_hash and m_val) or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def timed_steps(lat, steps, warmup):
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    s = lat.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    lat.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3  # seconds
+
+
+def cavity_lattice(n, storage):
+    import workloads as W
+    from paper_1202_6351_amd import Lattice, Params
+    tau = W.cavity_tau(n, 0.1, 1000.0)
+    p = Params(n, n, tau=tau, bc=("wall",) * 4, wall_u=(0, 0, 0, 0.1), storage=storage)
+    lat = Lattice(p, device="cuda:0")
+    lat.init_equilibrium(*W.at_rest(n, n, density_noise=1e-6, seed=2))
+    return lat, tau
+
+
+def taylor_green_lattice(n, storage, u0=0.05, tau=0.8):
+    import workloads as W
+    from paper_1202_6351_amd import Lattice, Params
+    lat = Lattice(Params(n, n, tau=tau, storage=storage), device="cuda:0")
+    lat.init_equilibrium(*W.taylor_green(n, u0, noise=1e-5, seed=0))
+    return lat
+
+
+def cpu_baseline(n, tau, budget_s=12.0):
+    """The FP64 oracle on the same cavity, first steps from the same initial
+    state, on all host threads; steps chosen to fill about budget_s."""
+    import oracle
+    import workloads as W
+    p = oracle.Params(n, n, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
+    f = oracle.init_state(p, *W.at_rest(n, n, density_noise=1e-6, seed=2))
+    t0 = time.perf_counter()
+    f = oracle.step(p, f, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(200, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.step(p, f, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(n * n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, lid-driven cavity {n}x{n} Re 1000, {steps} steps from the "
+                      f"benchmark's initial state ({dt:.1f} s)"}
+
+
+def precision_errors(n=512, steps=20000):
+    """Velocity and strain-rate relative error (Sec. III norm) of FP32, FP16
+    and BF16 storage against the FP64 path, Taylor-Green n x n, U0 0.05,
+    tau 0.8, noise 1e-5."""
+    import numpy as np
+    import torch
+    out = {}
+    ref = taylor_green_lattice(n, "fp64").step(steps).macroscopic()
+    ref = {k: v.cpu().numpy() for k, v in ref.items()}
+    den_u = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).sum()
+    for storage in ("fp32", "fp16", "bf16"):
+        m = taylor_green_lattice(n, storage).step(steps).macroscopic()
+        m = {k: v.cpu().numpy() for k, v in m.items()}
+        eu = np.sqrt((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2).sum() / den_u
+        es = np.abs(m["sxx"] - ref["sxx"]).sum() / np.abs(ref["sxx"]).sum()
+        out[storage] = {"u_rel_err": float(f"{eu:.3e}"), "sxx_rel_err": float(f"{es:.3e}")}
+    torch.cuda.synchronize()
+    return {"workload": f"taylor_green_{n}x{n}_u0.05_tau0.8_{steps}steps", "reference": "fp64 GPU path",
+            **out}
+
+
+def adjoint_rollout(n=512, T=2000, every=100):
+    """Forward + adjoint of the differentiable rollout (512 x 512 periodic,
+    force field N(0, 1e-6^2) seed 4, u0 = 0, Taylor-Green target U0 = 0.02)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1202_6351_amd import Params, rollout
+    k = 2 * math.pi / n
+    nu = (0.8 - 0.5) / 3
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    dec = math.exp(-2 * nu * k * k * T)
+    tgt = torch.from_numpy(np.stack([-0.02 * np.cos(k * x) * np.sin(k * y) * dec,
+                                     0.02 * np.sin(k * x) * np.cos(k * y) * dec])).cuda()
+    res = {}
+    for storage in ("fp32", "fp64"):
+        real = torch.float32 if storage == "fp32" else torch.float64
+        p = Params(n, n, tau=0.8, storage=storage)
+        F = torch.from_numpy(W.force_field(n, n, 1e-6, seed=4)).to("cuda", real).requires_grad_(True)
+        u0 = torch.zeros(2, n, n, dtype=real, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, u = rollout(p, F, u0, T, checkpoint_every=every)
+        loss = ((u - tgt) ** 2).sum(dim=0).mean()
+        loss.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[storage] = (dt, F.grad.double().cpu().numpy(), u0.grad.double().cpu().numpy())
+    dt = res["fp32"][0]
+    errF = np.abs(res["fp32"][1] - res["fp64"][1]).sum() / np.abs(res["fp64"][1]).sum()
+    erru = np.abs(res["fp32"][2] - res["fp64"][2]).sum() / np.abs(res["fp64"][2]).sum()
+    return {"workload": f"rollout_{n}x{n}_fp32_T{T}_ckpt{every}", "mlups": round(n * n * T / dt / 1e6, 1),
+            "seconds": round(dt, 3), "grad_force_rel_err_vs_fp64": float(f"{errF:.3e}"),
+            "grad_u0_rel_err_vs_fp64": float(f"{erru:.3e}")}
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size, so that counter runs can scale the
+    step kernel's FETCH_SIZE / WRITE_SIZE by what the same counters read for
+    it."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
+    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64"], default=None,
+                    help="time one storage mode only (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU domain decomposition is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+
+    if args.only in ("fp16", "bf16", "fp64"):
+        n = 8192 if args.only != "fp64" else 4096
+        lat = taylor_green_lattice(n, args.only) if args.only != "fp64" else cavity_lattice(n, "fp64")[0]
+        dt = timed_steps(lat, args.steps, args.warmup)
+        mlups = n * n * args.steps / dt / 1e6
+        print(json.dumps({"only": args.only, "n": n, "mlups": round(mlups, 1),
+                          "gbs": round(mlups * BYTES_PER_NODE[args.only] / 1e3, 1)}))
+        return
+
+    n = args.n
+    lat, tau = cavity_lattice(n, "fp32")
+    dt = timed_steps(lat, args.steps, args.warmup)
+    mlups = n * n * args.steps / dt / 1e6
+    per_launch = dt / args.steps
+    achieved = BYTES_PER_NODE["fp32"] * n * n / per_launch / 1e9
+    d = lat.diagnostics()  # raises on a non-finite state
+    traffic = measured_traffic() if n == 4096 else None
+    line = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"cavity_{n}x{n}_re1000_fp32", "nx": n, "ny": n, "tau": round(tau, 6),
+                   "lid_u": 0.1, "storage": "fp32", "bc": "halfway bounce-back walls, moving lid"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic)},
+        "mass_drift_rel": float(f"{abs(d[0] / (n * n) - 1.0):.2e}"),
+    }
+    del lat
+    torch.cuda.empty_cache()
+    if args.only is None and not args.no_forms:
+        forms = {}
+        for storage in ("fp16", "bf16"):
+            l16 = taylor_green_lattice(8192, storage)
+            steps16 = max(10, args.steps // 4)
+            dt16 = timed_steps(l16, steps16, max(1, args.warmup // 4))
+            m16 = 8192 * 8192 * steps16 / dt16 / 1e6
+            a16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / steps16) / 1e9
+            forms[f"{storage}_dev"] = {"workload": "taylor_green_8192x8192", "mlups": round(m16, 1),
+                                       "achieved_gbs": round(a16, 1), "frac": round(a16 / HBM_PEAK_GBS, 4)}
+            del l16
+            torch.cuda.empty_cache()
+        forms["error_vs_fp64"] = precision_errors()
+        forms["fwd_adjoint"] = adjoint_rollout()
+        line["forms"] = forms
+    if args.only is None and not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, tau)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

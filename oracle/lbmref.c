@@ -283,6 +283,7 @@ static inline void node_force(const lbmref_params* p, int y, int x, double* Fx,
  * Sec. II) from node fields rho, ux, uy, each [ny][nx]. */
 void lbmref_init(const lbmref_params* p, const double* rho, const double* ux,
                  const double* uy, double* f) {
+#pragma omp parallel for schedule(static) if ((int64_t)p->nx * p->ny >= 16384)
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
       const size_t c = (size_t)y * p->nx + x;

@@ -1,0 +1,350 @@
+// cascade.h -- per-node arithmetic of the cascaded (central-moment) D2Q9
+// collision with central-moment forcing, and its reverse (transposed
+// Jacobian), for gfx950.
+//
+// What is computed (Ning & Premnath, Section II): with rho = sum f-bar and
+// u = (sum f-bar e + F/2)/rho, the central moments
+// C_mn = sum_a f-bar_a (e_ax - u_x)^m (e_ay - u_y)^n are relaxed each at its
+// own rate towards the transformed attractors (Sec. II, the kappa-bar^eq
+// list; the explicit collision kernels g3..g8 plus the source S reach
+// exactly this), the first-order ones going from -F/2 to +F/2 (the source's
+// central moments are (0, F_x, F_y, 0, ...)):
+//   C*_00 = rho, C*_10 = F_x/2, C*_01 = F_y/2,
+//   (C_20 + C_02)* = (C_20 + C_02) + w3 (2 rho/3 - (C_20 + C_02)),
+//   (C_20 - C_02)* = (1 - w4)(C_20 - C_02),  C*_11 = (1 - w5) C_11,
+//   C*_21 = (1 - w6) C_21,  C*_12 = (1 - w7) C_12,
+//   C*_22 = C_22 + w8 (rho/9 - C_22),
+// and f~-bar is the D2Q9 vector with those central moments.
+//
+// How (differs from the paper's route, same result): D2Q9 is the tensor
+// product of {-1, 0, +1} with itself, so the monomial-moment transform, the
+// binomial shift to central moments (Sec. II binomial formula) and their
+// inverses all factor into 3-point operations along x then y.  Everything is
+// written for the deviation d = f-bar - w rho0 from the rest equilibrium:
+// the rest part's raw moments rho0 (1,0,1/3) x (1,0,1/3) map to the central
+// moments rho0 Cw(u) with Cw = (1, -u, 1/3 + u^2) per axis, so the
+// relaxation can be carried out on Delta C = C - rho0 Cw whose every term is
+// of order |u| or rho - rho0.  No O(1) quantity is ever cancelled, which is
+// what lets FP32 arithmetic and 16-bit storage hold small velocities.
+//
+// The collision is applied as an increment, as the paper writes it
+// (f~-bar = f-bar + K g + S): Delta C = C* - C is formed in central-moment
+// space (its conserved part is exactly (0, F_x, F_y)), shifted back to raw
+// moments and inverted, and only then added to the incoming d.  Rounding in
+// the transforms is then relative to the small non-equilibrium change, not
+// to d itself; with the full post-collision moments instead, FP32 rounding
+// in the inverse transform repeats identically every step of a steady flow
+// and acts as a spurious body force (measured: 7e-5 relative velocity error
+// on a 256 x 64 Poiseuille channel after 4000 steps, against 1e-7 with the
+// increment).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+// Direction order of Section II.  DIR[J][I] is the direction with
+// e_x = I - 1, e_y = J - 1.
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr int DIR[3][3] = {{7, 4, 8}, {3, 0, 1}, {6, 2, 5}};
+
+template <typename R>
+struct Rates {
+  R w3, w4, w5, w6, w7, w8;        // relaxation rates omega_3..omega_8
+  R k3, k4, k5, k6, k7, k8;        // 1 - omega
+  R rho0;                          // reference density of the deviations
+};
+
+// Intermediates of the forward pass that the reverse pass needs.
+template <typename R>
+struct NodeFwd {
+  R M[3][3];   // raw moments of d, M[m][n] ~ e_x^m e_y^n
+  R X[3][3];   // after the x shift to central
+  R D[3][3];   // change of the central moments in the collision
+  R Y[3][3];   // after the y shift of D back to raw
+  R ux, uy, inv_rho, drho;
+};
+
+// ------------------------------------------------------ 3-point operators
+// Moments of (p-, p0, p+) on {-1, 0, +1}: m0 = sum, m1 = p+ - p-, m2 = p+ + p-.
+template <typename R>
+__device__ __forceinline__ void ax_mom(R pm, R p0, R pp, R& m0, R& m1, R& m2) {
+  m2 = pp + pm;
+  m1 = pp - pm;
+  m0 = m2 + p0;
+}
+template <typename R>
+__device__ __forceinline__ void ax_mom_T(R a0, R a1, R a2, R& apm, R& ap0, R& app) {
+  ap0 = a0;
+  apm = a0 - a1 + a2;
+  app = a0 + a1 + a2;
+}
+// Inverse: p0 = m0 - m2, p-+ = (m2 -+ m1)/2.
+template <typename R>
+__device__ __forceinline__ void ax_inv(R m0, R m1, R m2, R& pm, R& p0, R& pp) {
+  p0 = m0 - m2;
+  pm = R(0.5) * (m2 - m1);
+  pp = R(0.5) * (m2 + m1);
+}
+template <typename R>
+__device__ __forceinline__ void ax_inv_T(R apm, R ap0, R app, R& a0, R& a1, R& a2) {
+  a0 = ap0;
+  a1 = R(0.5) * (app - apm);
+  a2 = R(0.5) * (app + apm) - ap0;
+}
+// Shift raw -> central about u: c1 = m1 - u m0, c2 = m2 - 2u m1 + u^2 m0.
+template <typename R>
+__device__ __forceinline__ void ax_ctr(R u, R m0, R m1, R m2, R& c0, R& c1, R& c2) {
+  c0 = m0;
+  c1 = m1 - u * m0;
+  c2 = m2 - u * (m1 + c1);
+}
+// Transpose of ax_ctr at inputs (m0, m1, m2); accumulates d/du into au.
+template <typename R>
+__device__ __forceinline__ void ax_ctr_T(R u, R m0, R m1, R a0, R a1, R a2,
+                                         R& am0, R& am1, R& am2, R& au) {
+  const R c1 = m1 - u * m0;
+  am2 = a2;
+  am1 = a1 - R(2) * u * a2;
+  am0 = a0 - u * (a1 - u * a2);
+  au += -m0 * a1 - R(2) * c1 * a2;
+}
+// Shift central -> raw about u: m1 = c1 + u c0, m2 = c2 + 2u c1 + u^2 c0.
+template <typename R>
+__device__ __forceinline__ void ax_unc(R u, R c0, R c1, R c2, R& m0, R& m1, R& m2) {
+  m0 = c0;
+  m1 = c1 + u * c0;
+  m2 = c2 + u * (c1 + m1);
+}
+template <typename R>
+__device__ __forceinline__ void ax_unc_T(R u, R c0, R c1, R a0, R a1, R a2,
+                                         R& ac0, R& ac1, R& ac2, R& au) {
+  const R m1 = c1 + u * c0;
+  ac2 = a2;
+  ac1 = a1 + R(2) * u * a2;
+  ac0 = a0 + u * (a1 + u * a2);
+  au += c0 * a1 + R(2) * m1 * a2;
+}
+
+// --------------------------------------------------------------- relaxation
+// Transformed equilibrium of Sec. II in deviation form: central moments
+// (rho, hFx, hFy, rho/3, rho/3, 0, 0, 0, rho/9) about u minus rho0 Cw(u).
+// With hF = -F/2 this is f^eq - S/2 (the initial state); its entries of
+// order >= 2 are the relaxation targets of the collision.
+template <typename R>
+__device__ __forceinline__ void equilibrium_cm(R r0, R drho, R ux, R uy, R hFx, R hFy, R Cs[3][3]) {
+  const R ux2 = ux * ux, uy2 = uy * uy;
+  Cs[0][0] = drho;
+  Cs[1][0] = hFx + r0 * ux;
+  Cs[0][1] = hFy + r0 * uy;
+  Cs[2][0] = R(1.0 / 3.0) * drho - r0 * ux2;
+  Cs[0][2] = R(1.0 / 3.0) * drho - r0 * uy2;
+  Cs[1][1] = -r0 * (ux * uy);
+  Cs[2][1] = r0 * uy * (R(1.0 / 3.0) + ux2);
+  Cs[1][2] = r0 * ux * (R(1.0 / 3.0) + uy2);
+  Cs[2][2] = R(1.0 / 9.0) * drho - r0 * (R(1.0 / 3.0) * (ux2 + uy2) + ux2 * uy2);
+}
+
+template <typename R>
+__device__ __forceinline__ void equilibrium_cm_T(R r0, R ux, R uy, const R aCs[3][3], R& adrho,
+                                                 R& aux, R& auy, R& ahFx, R& ahFy) {
+  const R ux2 = ux * ux, uy2 = uy * uy;
+  adrho += aCs[0][0] + R(1.0 / 3.0) * (aCs[2][0] + aCs[0][2]) + R(1.0 / 9.0) * aCs[2][2];
+  ahFx += aCs[1][0];
+  ahFy += aCs[0][1];
+  aux += r0 * aCs[1][0] - R(2) * r0 * ux * aCs[2][0] - r0 * uy * aCs[1][1] +
+         R(2) * r0 * ux * uy * aCs[2][1] + r0 * (R(1.0 / 3.0) + uy2) * aCs[1][2] -
+         r0 * (R(2.0 / 3.0) * ux + R(2) * ux * uy2) * aCs[2][2];
+  auy += r0 * aCs[0][1] - R(2) * r0 * uy * aCs[0][2] - r0 * ux * aCs[1][1] +
+         r0 * (R(1.0 / 3.0) + ux2) * aCs[2][1] + R(2) * r0 * ux * uy * aCs[1][2] -
+         r0 * (R(2.0 / 3.0) * uy + R(2) * uy * ux2) * aCs[2][2];
+}
+
+// Collision increment of the central moments, Delta C = C* - C:
+//   Delta C_00 = 0, Delta C_10 = F_x, Delta C_01 = F_y (-F/2 -> +F/2),
+//   Delta(C_20 + C_02) = w3 (E_s - (C_20 + C_02)),
+//   Delta(C_20 - C_02) = w4 (E_d - (C_20 - C_02)),
+//   Delta C_11 = w5 (E_11 - C_11), Delta C_21 = w6 (E_21 - C_21),
+//   Delta C_12 = w7 (E_12 - C_12), Delta C_22 = w8 (E_22 - C_22),
+// E being the equilibrium central moments (deviation form).
+template <typename R>
+__device__ __forceinline__ void relax_delta(const Rates<R>& r, R drho, R ux, R uy, R Fx, R Fy,
+                                            const R C[3][3], R D[3][3]) {
+  R E[3][3];
+  equilibrium_cm(r.rho0, drho, ux, uy, R(0), R(0), E);
+  D[0][0] = R(0);
+  D[1][0] = Fx;
+  D[0][1] = Fy;
+  const R ds = r.w3 * ((E[2][0] + E[0][2]) - (C[2][0] + C[0][2]));
+  const R dd = r.w4 * ((E[2][0] - E[0][2]) - (C[2][0] - C[0][2]));
+  D[2][0] = R(0.5) * (ds + dd);
+  D[0][2] = R(0.5) * (ds - dd);
+  D[1][1] = r.w5 * (E[1][1] - C[1][1]);
+  D[2][1] = r.w6 * (E[2][1] - C[2][1]);
+  D[1][2] = r.w7 * (E[1][2] - C[1][2]);
+  D[2][2] = r.w8 * (E[2][2] - C[2][2]);
+}
+
+// Reverse of relax_delta: cotangent aD -> aC (C_00, C_10, C_01 get none) and
+// accumulations into adrho, aux, auy, aFx, aFy.
+template <typename R>
+__device__ __forceinline__ void relax_delta_T(const Rates<R>& r, R ux, R uy, const R aD[3][3],
+                                              R aC[3][3], R& adrho, R& aux, R& auy, R& aFx,
+                                              R& aFy) {
+  aFx += aD[1][0];
+  aFy += aD[0][1];
+  const R as = r.w3 * R(0.5) * (aD[2][0] + aD[0][2]);  // cotangent of the s target
+  const R ad = r.w4 * R(0.5) * (aD[2][0] - aD[0][2]);  // cotangent of the d target
+  R aE[3][3];
+  aE[0][0] = R(0);
+  aE[1][0] = R(0);
+  aE[0][1] = R(0);
+  aE[2][0] = as + ad;
+  aE[0][2] = as - ad;
+  aE[1][1] = r.w5 * aD[1][1];
+  aE[2][1] = r.w6 * aD[2][1];
+  aE[1][2] = r.w7 * aD[1][2];
+  aE[2][2] = r.w8 * aD[2][2];
+  aC[0][0] = R(0);
+  aC[1][0] = R(0);
+  aC[0][1] = R(0);
+  aC[2][0] = -aE[2][0];
+  aC[0][2] = -aE[0][2];
+  aC[1][1] = -aE[1][1];
+  aC[2][1] = -aE[2][1];
+  aC[1][2] = -aE[1][2];
+  aC[2][2] = -aE[2][2];
+  R unused_x = R(0), unused_y = R(0);
+  equilibrium_cm_T(r.rho0, ux, uy, aE, adrho, aux, auy, unused_x, unused_y);
+}
+
+// ------------------------------------------------------------ node passes
+// Raw moments of a node's d (x then y).
+template <typename R>
+__device__ __forceinline__ void raw_moments(const R d[9], R M[3][3]) {
+  R A[3][3];  // A[J][m]
+#pragma unroll
+  for (int J = 0; J < 3; ++J) ax_mom(d[DIR[J][0]], d[DIR[J][1]], d[DIR[J][2]], A[J][0], A[J][1], A[J][2]);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) ax_mom(A[0][m], A[1][m], A[2][m], M[m][0], M[m][1], M[m][2]);
+}
+
+// Central moments (deviation form) Delta C about u from raw moments M;
+// X receives the intermediate after the x shift.
+template <typename R>
+__device__ __forceinline__ void central(R ux, R uy, const R M[3][3], R X[3][3], R C[3][3]) {
+#pragma unroll
+  for (int n = 0; n < 3; ++n) ax_ctr(ux, M[0][n], M[1][n], M[2][n], X[0][n], X[1][n], X[2][n]);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) ax_ctr(uy, X[m][0], X[m][1], X[m][2], C[m][0], C[m][1], C[m][2]);
+}
+
+// Populations (deviation form) with central moments Cs about u; Y receives
+// the intermediate after the y shift.  Linear in Cs: also maps a change of
+// central moments to the change of populations.
+template <typename R>
+__device__ __forceinline__ void populations(R ux, R uy, const R Cs[3][3], R Y[3][3], R out[9]) {
+  R Mo[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) ax_unc(uy, Cs[m][0], Cs[m][1], Cs[m][2], Y[m][0], Y[m][1], Y[m][2]);
+#pragma unroll
+  for (int n = 0; n < 3; ++n) ax_unc(ux, Y[0][n], Y[1][n], Y[2][n], Mo[0][n], Mo[1][n], Mo[2][n]);
+  R B[3][3];  // B[J][m]
+#pragma unroll
+  for (int m = 0; m < 3; ++m) ax_inv(Mo[m][0], Mo[m][1], Mo[m][2], B[0][m], B[1][m], B[2][m]);
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+    ax_inv(B[J][0], B[J][1], B[J][2], out[DIR[J][0]], out[DIR[J][1]], out[DIR[J][2]]);
+}
+
+// Reverse of populations(): cotangent aout of the output -> aCs; accumulates
+// d/du into aux, auy.
+template <typename R>
+__device__ __forceinline__ void populations_T(R ux, R uy, const R Cs[3][3], const R Y[3][3],
+                                              const R aout[9], R aCs[3][3], R& aux, R& auy) {
+  R aB[3][3];
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+    ax_inv_T(aout[DIR[J][0]], aout[DIR[J][1]], aout[DIR[J][2]], aB[J][0], aB[J][1], aB[J][2]);
+  R aMo[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) ax_inv_T(aB[0][m], aB[1][m], aB[2][m], aMo[m][0], aMo[m][1], aMo[m][2]);
+  R aY[3][3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n)
+    ax_unc_T(ux, Y[0][n], Y[1][n], aMo[0][n], aMo[1][n], aMo[2][n], aY[0][n], aY[1][n], aY[2][n], aux);
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    ax_unc_T(uy, Cs[m][0], Cs[m][1], aY[m][0], aY[m][1], aY[m][2], aCs[m][0], aCs[m][1], aCs[m][2], auy);
+}
+
+// Hydrodynamic fields from the raw moments of d (Sec. II): rho = rho0 +
+// M_00, u = (M_10 + F_x/2, M_01 + F_y/2)/rho (the rest part has no momentum).
+template <typename R>
+__device__ __forceinline__ void node_fields(const Rates<R>& r, const R M[3][3], R Fx, R Fy,
+                                            R& drho, R& inv_rho, R& ux, R& uy) {
+  drho = M[0][0];
+  inv_rho = R(1) / (r.rho0 + drho);
+  ux = (M[1][0] + R(0.5) * Fx) * inv_rho;
+  uy = (M[0][1] + R(0.5) * Fy) * inv_rho;
+}
+
+// One collision: d (pre-collision deviations) -> out (post-collision), with
+// the intermediates in s.  out = d + T^-1 Sh(+u) Delta C (see header).
+template <typename R>
+__device__ __forceinline__ void collide(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9],
+                                        NodeFwd<R>& s) {
+  raw_moments(d, s.M);
+  node_fields(r, s.M, Fx, Fy, s.drho, s.inv_rho, s.ux, s.uy);
+  R C[3][3];
+  central(s.ux, s.uy, s.M, s.X, C);
+  relax_delta(r, s.drho, s.ux, s.uy, Fx, Fy, C, s.D);
+  R inc[9];
+  populations(s.ux, s.uy, s.D, s.Y, inc);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) out[k] = d[k] + inc[k];
+}
+
+// Transposed Jacobian of collide() at the state recorded in s: given the
+// cotangent aout of the output, returns the cotangent ad of d and adds the
+// force cotangent to aFx, aFy.
+template <typename R>
+__device__ __forceinline__ void collide_T(const Rates<R>& r, const NodeFwd<R>& s, const R aout[9],
+                                          R ad[9], R& aFx, R& aFy) {
+  R aux = R(0), auy = R(0), adrho = R(0);
+  R aD[3][3];
+  populations_T(s.ux, s.uy, s.D, s.Y, aout, aD, aux, auy);
+  R aC[3][3];
+  relax_delta_T(r, s.ux, s.uy, aD, aC, adrho, aux, auy, aFx, aFy);
+  R aX[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    ax_ctr_T(s.uy, s.X[m][0], s.X[m][1], aC[m][0], aC[m][1], aC[m][2], aX[m][0], aX[m][1], aX[m][2], auy);
+  R aM[3][3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n)
+    ax_ctr_T(s.ux, s.M[0][n], s.M[1][n], aX[0][n], aX[1][n], aX[2][n], aM[0][n], aM[1][n], aM[2][n], aux);
+  // u = j / rho with j = (M_10 + F_x/2, M_01 + F_y/2), rho = rho0 + M_00.
+  const R ajx = aux * s.inv_rho, ajy = auy * s.inv_rho;
+  aM[0][0] += adrho - (aux * s.ux + auy * s.uy) * s.inv_rho;
+  aM[1][0] += ajx;
+  aM[0][1] += ajy;
+  aFx += R(0.5) * ajx;
+  aFy += R(0.5) * ajy;
+  R aA[3][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) ax_mom_T(aM[m][0], aM[m][1], aM[m][2], aA[0][m], aA[1][m], aA[2][m]);
+  // out = d + increment: the identity path adds aout to the cotangent of d.
+#pragma unroll
+  for (int J = 0; J < 3; ++J) {
+    R a0, a1, a2;
+    ax_mom_T(aA[J][0], aA[J][1], aA[J][2], a0, a1, a2);
+    ad[DIR[J][0]] = aout[DIR[J][0]] + a0;
+    ad[DIR[J][1]] = aout[DIR[J][1]] + a1;
+    ad[DIR[J][2]] = aout[DIR[J][2]] + a2;
+  }
+}
+
+}  // namespace lbm

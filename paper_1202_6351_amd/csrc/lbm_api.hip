@@ -1,0 +1,336 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm.h:
+// parameter validation, context state (ping-pong index, time), kernel
+// arguments, error reporting.  Kernels live in lbm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lbm.h"
+#include "lbm_launch.h"
+
+struct lbm_ctx {
+  lbm_params p;
+  lbm::KArgsAny args;
+  void* lat[2];
+  int cur;            // index of the lattice holding the current state
+  int64_t t;          // steps since the state was set
+  bool has_state;
+  bool has_force_field;
+  hipStream_t stream;
+  double* diag_scratch;  // device: partial sums (diag_blocks * 4) + result (4)
+  int diag_blocks;
+  int64_t pitch, lattice_bytes;
+  char err[512];
+};
+
+namespace {
+
+thread_local char g_create_err[512] = "";
+
+int storage_size(int32_t s) {
+  switch (s) {
+    case LBM_FP64: return 8;
+    case LBM_FP32: return 4;
+    case LBM_FP16_DEV: return 2;
+    case LBM_BF16_DEV: return 2;
+    default: return 0;
+  }
+}
+
+int real_size(int32_t s) { return s == LBM_FP64 ? 8 : 4; }
+
+void set_err(char* buf, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, 512, fmt, ap);
+  va_end(ap);
+}
+
+// Validate a parameter set; message into buf.
+bool validate(const lbm_params* p, char* buf) {
+  if (!p) { set_err(buf, "params is NULL"); return false; }
+  if (p->nx < 2 || p->ny < 2) { set_err(buf, "grid %d x %d: need nx, ny >= 2", p->nx, p->ny); return false; }
+  if (storage_size(p->storage) == 0) { set_err(buf, "unknown storage mode %d", p->storage); return false; }
+  const double om[5] = {p->omega_nu, p->omega3, p->omega6, p->omega7, p->omega8};
+  const char* nm[5] = {"omega_nu", "omega3", "omega6", "omega7", "omega8"};
+  for (int i = 0; i < 5; ++i)
+    if (!(om[i] > 0.0 && om[i] < 2.0)) { set_err(buf, "%s = %g outside (0, 2)", nm[i], om[i]); return false; }
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) { set_err(buf, "rho0 = %g must be > 0", p->rho0); return false; }
+  if (!std::isfinite(p->fx) || !std::isfinite(p->fy)) { set_err(buf, "body force is not finite"); return false; }
+  for (int s = 0; s < 4; ++s) {
+    if (p->bc[s] != LBM_PERIODIC && p->bc[s] != LBM_WALL) { set_err(buf, "bc[%d] = %d unknown", s, p->bc[s]); return false; }
+    if (!std::isfinite(p->wall_u[s])) { set_err(buf, "wall_u[%d] not finite", s); return false; }
+    if (p->bc[s] == LBM_PERIODIC && p->wall_u[s] != 0.0) {
+      set_err(buf, "wall_u[%d] = %g on a periodic side", s, p->wall_u[s]);
+      return false;
+    }
+  }
+  if ((p->bc[0] == LBM_PERIODIC) != (p->bc[1] == LBM_PERIODIC)) { set_err(buf, "x sides: periodic on one side only"); return false; }
+  if ((p->bc[2] == LBM_PERIODIC) != (p->bc[3] == LBM_PERIODIC)) { set_err(buf, "y sides: periodic on one side only"); return false; }
+  const int64_t pitch = ((int64_t)p->nx + 63) / 64 * 64;
+  if ((int64_t)p->ny * pitch >= ((int64_t)1 << 31)) { set_err(buf, "lattice plane of %lld elements exceeds 2^31", (long long)(p->ny * pitch)); return false; }
+  return true;
+}
+
+template <typename R>
+void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs<R>& a) {
+  lbm::Geom& g = a.g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.pitch = (int32_t)pitch;
+  g.plane = (int64_t)p->ny * pitch;
+  // Tile width: the widest power of two in {64, 128, 256} not beyond the
+  // padded row, so narrow lattices still fill whole wavefronts.
+  g.tx_shift = pitch >= 256 ? 8 : (pitch >= 128 ? 7 : 6);
+  const int tx = 1 << g.tx_shift, ty = 256 / tx;
+  g.tiles_x = (int32_t)((p->nx + tx - 1) / tx);
+  g.tiles_y = (int32_t)((p->ny + ty - 1) / ty);
+  for (int s = 0; s < 4; ++s) g.wall[s] = p->bc[s] == LBM_WALL;
+  a.w[0] = (R)p->omega3;
+  a.w[1] = (R)p->omega_nu;
+  a.w[2] = (R)p->omega_nu;
+  a.w[3] = (R)p->omega6;
+  a.w[4] = (R)p->omega7;
+  a.w[5] = (R)p->omega8;
+  a.rho0 = (R)p->rho0;
+  a.fx = (R)p->fx;
+  a.fy = (R)p->fy;
+  a.force = (const R*)force;
+  // Moving-wall term 6 rho0 w_a (e_a . U_wall) per side: x walls move in y,
+  // y walls move in x.
+  static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                              1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  for (int s = 0; s < 4; ++s)
+    for (int k = 0; k < 9; ++k) {
+      const double tang = s < 2 ? EY[k] : EX[k];
+      a.wadd[s * 9 + k] = (R)(6.0 * p->rho0 * W[k] * tang * p->wall_u[s]);
+    }
+}
+
+bool aligned(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
+
+lbm_status dev_err(lbm_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return LBM_OK;
+  set_err(c->err, "%s: %s", what, hipGetErrorString(e));
+  return LBM_EDEVICE;
+}
+
+lbm_status inval(lbm_ctx* c, const char* msg) {
+  set_err(c->err, "%s", msg);
+  return LBM_EINVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_lattice_layout(const lbm_params* p, int64_t* pitch, int64_t* bytes) {
+  char buf[512];
+  if (!validate(p, buf)) { set_err(g_create_err, "%s", buf); return LBM_EINVAL; }
+  const int64_t pt = ((int64_t)p->nx + 63) / 64 * 64;
+  if (pitch) *pitch = pt;
+  if (bytes) *bytes = 9 * (int64_t)p->ny * pt * storage_size(p->storage);
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* force_field,
+                      void* stream, lbm_ctx** out) {
+  if (!out) { set_err(g_create_err, "out is NULL"); return LBM_EINVAL; }
+  *out = nullptr;
+  if (!validate(p, g_create_err)) return LBM_EINVAL;
+  if (!lat0 || !lat1 || lat0 == lat1) { set_err(g_create_err, "need two distinct lattice buffers"); return LBM_EINVAL; }
+  if (!aligned(lat0) || !aligned(lat1) || (force_field && !aligned(force_field))) {
+    set_err(g_create_err, "device buffers must be 256-byte aligned");
+    return LBM_EINVAL;
+  }
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) { set_err(g_create_err, "out of host memory"); return LBM_EDEVICE; }
+  c->p = *p;
+  c->pitch = ((int64_t)p->nx + 63) / 64 * 64;
+  c->lattice_bytes = 9 * (int64_t)p->ny * c->pitch * storage_size(p->storage);
+  c->lat[0] = lat0;
+  c->lat[1] = lat1;
+  c->cur = 0;
+  c->t = 0;
+  c->has_state = false;
+  c->has_force_field = force_field != nullptr;
+  c->stream = (hipStream_t)stream;
+  c->args.storage = p->storage;
+  if (p->storage == LBM_FP64) fill_args<double>(p, c->pitch, force_field, c->args.d);
+  else fill_args<float>(p, c->pitch, force_field, c->args.f);
+  // Diagnostics: a fixed number of blocks (enough to fill 256 CUs), so the
+  // reduction order does not depend on the grid size.
+  c->diag_blocks = 1024;
+  hipError_t e = hipMalloc((void**)&c->diag_scratch, sizeof(double) * (c->diag_blocks * 4 + 4));
+  if (e != hipSuccess) {
+    set_err(g_create_err, "hipMalloc(diagnostics scratch): %s", hipGetErrorString(e));
+    delete c;
+    return LBM_EDEVICE;
+  }
+  c->err[0] = 0;
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->diag_scratch) (void)hipFree(c->diag_scratch);
+  delete c;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_create_err; }
+
+lbm_status lbm_set_stream(lbm_ctx* c, void* stream) {
+  if (!c) return LBM_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+void* lbm_current_lattice(const lbm_ctx* c) { return c ? c->lat[c->cur] : nullptr; }
+
+lbm_status lbm_init_equilibrium(lbm_ctx* c, const void* rho, const void* ux, const void* uy) {
+  if (!c) return LBM_EINVAL;
+  if (!rho || !ux || !uy) return inval(c, "init_equilibrium: rho, ux, uy must be non-NULL");
+  lbm_status s = dev_err(c, lbm::launch_init(c->args, rho, ux, uy, c->lat[0], c->stream), "init kernel");
+  if (s != LBM_OK) return s;
+  c->cur = 0;
+  c->t = 0;
+  c->has_state = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const void* f) {
+  if (!c) return LBM_EINVAL;
+  if (!f) return inval(c, "set_populations: f is NULL");
+  lbm_status s = dev_err(c, lbm::launch_set(c->args, f, c->lat[0], c->stream), "set kernel");
+  if (s != LBM_OK) return s;
+  c->cur = 0;
+  c->t = 0;
+  c->has_state = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, void* f) {
+  if (!c) return LBM_EINVAL;
+  if (!f) return inval(c, "get_populations: f is NULL");
+  if (!c->has_state) { set_err(c->err, "get_populations before the state was set"); return LBM_ESTATE; }
+  return dev_err(c, lbm::launch_get(c->args, c->lat[c->cur], f, c->stream), "get kernel");
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0) return inval(c, "step: n < 0");
+  if (!c->has_state) { set_err(c->err, "step before the state was set"); return LBM_ESTATE; }
+  for (int64_t k = 0; k < n; ++k) {
+    lbm_status s = dev_err(c, lbm::launch_step(c->args, c->lat[c->cur], c->lat[c->cur ^ 1], c->stream),
+                           "step kernel");
+    if (s != LBM_OK) return s;
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step_between(lbm_ctx* c, const void* src, void* dst) {
+  if (!c) return LBM_EINVAL;
+  if (!src || !dst || src == dst) return inval(c, "step_between: need distinct non-NULL src, dst");
+  if (!aligned(src) || !aligned(dst)) return inval(c, "step_between: buffers must be 256-byte aligned");
+  return dev_err(c, lbm::launch_step(c->args, src, dst, c->stream), "step kernel");
+}
+
+lbm_status lbm_snapshot(lbm_ctx* c, void* dst) {
+  if (!c) return LBM_EINVAL;
+  if (!dst) return inval(c, "snapshot: dst is NULL");
+  if (!c->has_state) { set_err(c->err, "snapshot before the state was set"); return LBM_ESTATE; }
+  return dev_err(c, hipMemcpyAsync(dst, c->lat[c->cur], (size_t)c->lattice_bytes, hipMemcpyDeviceToDevice, c->stream),
+                 "snapshot copy");
+}
+
+lbm_status lbm_restore(lbm_ctx* c, const void* src, int64_t t) {
+  if (!c) return LBM_EINVAL;
+  if (!src) return inval(c, "restore: src is NULL");
+  if (t < 0) return inval(c, "restore: t < 0");
+  lbm_status s = dev_err(c, hipMemcpyAsync(c->lat[c->cur], src, (size_t)c->lattice_bytes, hipMemcpyDeviceToDevice,
+                                           c->stream), "restore copy");
+  if (s != LBM_OK) return s;
+  c->t = t;
+  c->has_state = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_macroscopic(lbm_ctx* c, void* rho, void* ux, void* uy, void* sxx, void* syy, void* sxy) {
+  if (!c) return LBM_EINVAL;
+  if (!c->has_state) { set_err(c->err, "macroscopic before the state was set"); return LBM_ESTATE; }
+  if (!rho && !ux && !uy && !sxx && !syy && !sxy) return LBM_OK;
+  return dev_err(c, lbm::launch_macro(c->args, c->lat[c->cur], rho, ux, uy, sxx, syy, sxy, c->stream),
+                 "macroscopic kernel");
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* c, double out[4]) {
+  if (!c) return LBM_EINVAL;
+  if (!out) return inval(c, "diagnostics: out is NULL");
+  if (!c->has_state) { set_err(c->err, "diagnostics before the state was set"); return LBM_ESTATE; }
+  double* res = c->diag_scratch + 4 * c->diag_blocks;
+  const double base = (double)c->p.nx * (double)c->p.ny * c->p.rho0;
+  lbm_status s = dev_err(c, lbm::launch_diag(c->args, c->lat[c->cur], c->diag_scratch, c->diag_blocks, base, res,
+                                             c->stream), "diagnostics kernel");
+  if (s != LBM_OK) return s;
+  s = dev_err(c, hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "diagnostics copy");
+  if (s != LBM_OK) return s;
+  s = dev_err(c, hipStreamSynchronize(c->stream), "diagnostics sync");
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(out[k])) {
+      set_err(c->err, "diagnostics: sum %d is not finite (unstable run)", k);
+      return LBM_EUNSTABLE;
+    }
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* c, const void* lat_prev, const void* mu_in, void* mu_out, void* grad_force) {
+  if (!c) return LBM_EINVAL;
+  if (c->p.storage != LBM_FP64 && c->p.storage != LBM_FP32) {
+    set_err(c->err, "adjoint needs FP64 or FP32 storage");
+    return LBM_EUNSUPPORTED;
+  }
+  if (!lat_prev || !mu_in || !mu_out || mu_in == mu_out) return inval(c, "adjoint_step: need lat_prev and distinct mu_in, mu_out");
+  if (grad_force && !c->has_force_field) return inval(c, "adjoint_step: grad_force needs a bound force field");
+  return dev_err(c, lbm::launch_adjoint_step(c->args, lat_prev, mu_in, mu_out, grad_force, c->stream),
+                 "adjoint step kernel");
+}
+
+lbm_status lbm_adjoint_macroscopic(lbm_ctx* c, const void* lat, const void* g_rho, const void* g_ux,
+                                   const void* g_uy, void* mu_out, void* grad_force) {
+  if (!c) return LBM_EINVAL;
+  if (c->p.storage != LBM_FP64 && c->p.storage != LBM_FP32) {
+    set_err(c->err, "adjoint needs FP64 or FP32 storage");
+    return LBM_EUNSUPPORTED;
+  }
+  if (!lat || !mu_out) return inval(c, "adjoint_macroscopic: need lat and mu_out");
+  if (grad_force && !c->has_force_field) return inval(c, "adjoint_macroscopic: grad_force needs a bound force field");
+  return dev_err(c, lbm::launch_adjoint_macro(c->args, lat, g_rho, g_ux, g_uy, mu_out, grad_force, c->stream),
+                 "adjoint macroscopic kernel");
+}
+
+lbm_status lbm_adjoint_init(lbm_ctx* c, const void* rho, const void* ux, const void* uy, const void* mu0,
+                            void* g_rho, void* g_ux, void* g_uy, void* grad_force) {
+  if (!c) return LBM_EINVAL;
+  if (c->p.storage != LBM_FP64 && c->p.storage != LBM_FP32) {
+    set_err(c->err, "adjoint needs FP64 or FP32 storage");
+    return LBM_EUNSUPPORTED;
+  }
+  if (!rho || !ux || !uy || !mu0) return inval(c, "adjoint_init: need rho, ux, uy, mu0");
+  if (grad_force && !c->has_force_field) return inval(c, "adjoint_init: grad_force needs a bound force field");
+  return dev_err(c, lbm::launch_adjoint_init(c->args, rho, ux, uy, mu0, g_rho, g_ux, g_uy, grad_force, c->stream),
+                 "adjoint init kernel");
+}
+
+}  // extern "C"

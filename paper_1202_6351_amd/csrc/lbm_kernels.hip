@@ -1,0 +1,587 @@
+// lbm_kernels.hip -- gfx950 kernels of the cascaded D2Q9 lattice Boltzmann
+// step (Ning & Premnath, Section II) with periodic, halfway bounce-back and
+// moving-wall boundaries (Section III), its diagnostics and its adjoint.
+//
+// Data layout in HBM: a lattice is nine planes [9][ny][pitch] of the storage
+// type S (double, float, _Float16 or __bf16), x fastest, each row 64-element
+// aligned; the stored value is the deviation d = f - w rho0 (w the D2Q9 rest
+// weights) of the post-collision populations of the previous step (pull
+// scheme).  One thread owns one node.  A step gathers the nine populations
+// streaming into the node (plane a at x - e_a: coalesced, misaligned by one
+// element for e_x != 0), collides in registers (cascade.h) and writes the
+// nine results to the other lattice at the node itself (aligned, coalesced,
+// non-temporal).  A link whose source lies beyond a wall reads the reversed
+// population of the node itself (halfway bounce-back) plus the moving-wall
+// term; walls are resolved per thread from (x, y) with selects, so there is
+// no mask array and the wall rows do not diverge from the interior.
+//
+// Launch shape: 256-thread blocks covering TX x (256/TX) nodes, TX in
+// {64, 128, 256} (a 64-wide wavefront spans one row segment); the 1-D block
+// index is remapped so that each of the 8 XCDs (blocks are dealt to XCDs
+// round-robin) processes one contiguous band of tiles, keeping the lines
+// shared between horizontally and vertically adjacent tiles in one L2.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cascade.h"
+#include "lbm_launch.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------ storage codec
+template <typename S> struct Codec;
+template <> struct Codec<double> {
+  using R = double;
+  __device__ static R load(double v) { return v; }
+  __device__ static double store(R v) { return v; }
+};
+template <> struct Codec<float> {
+  using R = float;
+  __device__ static R load(float v) { return v; }
+  __device__ static float store(R v) { return v; }
+};
+template <> struct Codec<_Float16> {
+  using R = float;
+  __device__ static R load(_Float16 v) { return (float)v; }
+  __device__ static _Float16 store(R v) { return (_Float16)v; }  // round to nearest even
+};
+template <> struct Codec<__bf16> {
+  using R = float;
+  __device__ static R load(__bf16 v) { return (float)v; }
+  __device__ static __bf16 store(R v) { return (__bf16)v; }  // round to nearest even
+};
+
+// D2Q9 rest weights.
+template <typename R>
+__device__ __forceinline__ R weight(int a) {
+  return a == 0 ? R(4.0 / 9.0) : (a < 5 ? R(1.0 / 9.0) : R(1.0 / 36.0));
+}
+
+// ------------------------------------------------------------- node index
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  // Blocks are dealt to the 8 XCDs round-robin; give XCD k the contiguous
+  // range of logical tiles [start_k, start_k + count_k).
+  const int q = nblocks >> 3, rem = nblocks & 7;
+  const int xcd = b & 7, local = b >> 3;
+  const int start = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+  return start + local;
+}
+
+struct NodePos {
+  int x, y;
+  bool valid;
+};
+
+__device__ __forceinline__ NodePos node_pos(const Geom& g) {
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
+  const int lx = (int)threadIdx.x & ((1 << g.tx_shift) - 1);
+  const int ly = (int)threadIdx.x >> g.tx_shift;
+  NodePos p;
+  p.x = (tx << g.tx_shift) + lx;
+  p.y = ty * (256 >> g.tx_shift) + ly;
+  p.valid = p.x < g.nx && p.y < g.ny;
+  return p;
+}
+
+// Neighbour coordinates with periodic wrap and the wall flags of a node.
+struct Edges {
+  int xm, xp, ym, yp;      // x-1, x+1, y-1, y+1 wrapped
+  bool wxl, wxh, wyl, wyh;  // node touches the x_lo / x_hi / y_lo / y_hi wall
+};
+
+__device__ __forceinline__ Edges edges(const Geom& g, int x, int y) {
+  Edges e;
+  e.xm = x == 0 ? g.nx - 1 : x - 1;
+  e.xp = x == g.nx - 1 ? 0 : x + 1;
+  e.ym = y == 0 ? g.ny - 1 : y - 1;
+  e.yp = y == g.ny - 1 ? 0 : y + 1;
+  e.wxl = (x == 0) && g.wall[0];
+  e.wxh = (x == g.nx - 1) && g.wall[1];
+  e.wyl = (y == 0) && g.wall[2];
+  e.wyh = (y == g.ny - 1) && g.wall[3];
+  return e;
+}
+
+// Where the population streaming into (x, y) along direction A comes from:
+// element offset into the lattice and the moving-wall term.  Fluid or
+// periodic link: plane A at (x - e_x, y - e_y).  Link crossing a wall
+// (halfway bounce-back): plane opp(A) at (x, y), plus 6 rho0 w_A (e_A .
+// U_wall) of each wall crossed (precomputed per side and direction in wadd).
+template <int A, typename R>
+__device__ __forceinline__ int64_t link_src(const Geom& g, const Edges& e, int x, int y,
+                                            const R* wadd, R& add) {
+  constexpr int ex = EX[A], ey = EY[A];
+  const bool hx = (ex == 1 && e.wxl) || (ex == -1 && e.wxh);
+  const bool hy = (ey == 1 && e.wyl) || (ey == -1 && e.wyh);
+  const int sx = ex == 1 ? e.xm : (ex == -1 ? e.xp : x);
+  const int sy = ey == 1 ? e.ym : (ey == -1 ? e.yp : y);
+  add = R(0);
+  if (ex != 0) add += hx ? wadd[(ex == 1 ? 0 : 1) * 9 + A] : R(0);
+  if (ey != 0) add += hy ? wadd[(ey == 1 ? 2 : 3) * 9 + A] : R(0);
+  const bool hit = hx || hy;
+  const int plane = hit ? OPP[A] : A;
+  const int off = hit ? y * g.pitch + x : sy * g.pitch + sx;
+  return (int64_t)plane * g.plane + off;
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void gather(const Geom& g, const R* wadd, const S* __restrict__ src,
+                                       int x, int y, R d[9]) {
+  const Edges e = edges(g, x, y);
+#define LBM_GATHER(A)                                          \
+  {                                                            \
+    R add;                                                     \
+    const int64_t i = link_src<A, R>(g, e, x, y, wadd, add);   \
+    d[A] = Codec<S>::load(src[i]) + add;                       \
+  }
+  LBM_GATHER(0) LBM_GATHER(1) LBM_GATHER(2) LBM_GATHER(3) LBM_GATHER(4)
+  LBM_GATHER(5) LBM_GATHER(6) LBM_GATHER(7) LBM_GATHER(8)
+#undef LBM_GATHER
+}
+
+// Inverse of gather(): write the pre-collision value v[a] of (x, y) to the
+// place the next gather reads it from (minus the wall term).  Every lattice
+// element is written exactly once over all nodes (streaming is a
+// permutation).
+template <typename S, typename R>
+__device__ __forceinline__ void scatter(const Geom& g, const R* wadd, S* __restrict__ dst, int x,
+                                        int y, const R v[9], bool subtract_wall) {
+  const Edges e = edges(g, x, y);
+#define LBM_SCATTER(A)                                          \
+  {                                                             \
+    R add;                                                      \
+    const int64_t i = link_src<A, R>(g, e, x, y, wadd, add);    \
+    dst[i] = Codec<S>::store(subtract_wall ? v[A] - add : v[A]); \
+  }
+  LBM_SCATTER(0) LBM_SCATTER(1) LBM_SCATTER(2) LBM_SCATTER(3) LBM_SCATTER(4)
+  LBM_SCATTER(5) LBM_SCATTER(6) LBM_SCATTER(7) LBM_SCATTER(8)
+#undef LBM_SCATTER
+}
+
+template <typename R>
+__device__ __forceinline__ void node_force(const KArgs<R>& a, int x, int y, R& Fx, R& Fy) {
+  if (a.force) {
+    const int64_t c = (int64_t)y * a.g.nx + x;
+    Fx = a.force[c];
+    Fy = a.force[(int64_t)a.g.nx * a.g.ny + c];
+  } else {
+    Fx = a.fx;
+    Fy = a.fy;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ Rates<R> rates(const KArgs<R>& a) {
+  Rates<R> r;
+  r.w3 = a.w[0]; r.w4 = a.w[1]; r.w5 = a.w[2]; r.w6 = a.w[3]; r.w7 = a.w[4]; r.w8 = a.w[5];
+  r.k3 = R(1) - r.w3; r.k4 = R(1) - r.w4; r.k5 = R(1) - r.w5;
+  r.k6 = R(1) - r.w6; r.k7 = R(1) - r.w7; r.k8 = R(1) - r.w8;
+  r.rho0 = a.rho0;
+  return r;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// One fused stream-and-collide step: src (state n) -> dst (state n+1).
+template <typename S>
+__global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a,
+                                              const S* __restrict__ src, S* __restrict__ dst) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  R d[9];
+  gather<S, R>(a.g, a.wadd, src, p.x, p.y, d);
+  R Fx, Fy;
+  node_force(a, p.x, p.y, Fx, Fy);
+  R out[9];
+  NodeFwd<R> s;
+  collide(rates(a), Fx, Fy, d, out, s);
+  const int64_t c = (int64_t)p.y * a.g.pitch + p.x;
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    __builtin_nontemporal_store(Codec<S>::store(out[k]), dst + (int64_t)k * a.g.plane + c);
+}
+
+// Initial state f-bar = f^eq - S/2 (transformed equilibrium with hF = -F/2).
+// The FP64 fields are turned into deviations before narrowing to R.
+template <typename S>
+__global__ __launch_bounds__(256) void k_init(KArgs<typename Codec<S>::R> a, const double* rho,
+                                              const double* ux, const double* uy, S* __restrict__ dst) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  const int64_t c = (int64_t)p.y * a.g.nx + p.x;
+  R Fx, Fy;
+  node_force(a, p.x, p.y, Fx, Fy);
+  const R drho = (R)(rho[c] - (double)a.rho0);
+  const R vx = (R)ux[c], vy = (R)uy[c];
+  R Cs[3][3], Y[3][3], v[9];
+  equilibrium_cm(a.rho0, drho, vx, vy, R(-0.5) * Fx, R(-0.5) * Fy, Cs);
+  populations(vx, vy, Cs, Y, v);
+  scatter<S, R>(a.g, a.wadd, dst, p.x, p.y, v, true);
+}
+
+// Arbitrary populations f-bar [9][ny][nx] (FP64) -> state.
+template <typename S>
+__global__ __launch_bounds__(256) void k_set(KArgs<typename Codec<S>::R> a, const double* f,
+                                             S* __restrict__ dst) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  const int64_t c = (int64_t)p.y * a.g.nx + p.x, n = (int64_t)a.g.nx * a.g.ny;
+  R v[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v[k] = (R)(f[k * n + c] - weight<double>(k) * (double)a.rho0);
+  scatter<S, R>(a.g, a.wadd, dst, p.x, p.y, v, true);
+}
+
+// State -> pre-collision populations f-bar [9][ny][nx] (FP64).
+template <typename S>
+__global__ __launch_bounds__(256) void k_get(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                             double* f) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  R d[9];
+  gather<S, R>(a.g, a.wadd, src, p.x, p.y, d);
+  const int64_t c = (int64_t)p.y * a.g.nx + p.x, n = (int64_t)a.g.nx * a.g.ny;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) f[k * n + c] = (double)d[k] + weight<double>(k) * (double)a.rho0;
+}
+
+// Hydrodynamic fields and strain rate of the current state.
+template <typename S>
+__global__ __launch_bounds__(256) void k_macro(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                               double* rho, double* ux, double* uy, double* sxx,
+                                               double* syy, double* sxy) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  R d[9];
+  gather<S, R>(a.g, a.wadd, src, p.x, p.y, d);
+  R Fx, Fy;
+  node_force(a, p.x, p.y, Fx, Fy);
+  const Rates<R> r = rates(a);
+  R M[3][3], X[3][3], C[3][3], drho, inv, vx, vy;
+  raw_moments(d, M);
+  node_fields(r, M, Fx, Fy, drho, inv, vx, vy);
+  const int64_t c = (int64_t)p.y * a.g.nx + p.x;
+  if (rho) rho[c] = (double)a.rho0 + (double)drho;
+  if (ux) ux[c] = vx;
+  if (uy) uy[c] = vy;
+  if (sxx || syy || sxy) {
+    central(vx, vy, M, X, C);
+    // Non-equilibrium second moments of f = f-bar + S/2 (the source has no
+    // second-order central moments): f3neq = C_20 + C_02 - 2 rho/3,
+    // f4neq = C_20 - C_02, f5neq = C_11, written in deviation form.
+    const R u2x = vx * vx, u2y = vy * vy;
+    const R f3 = (C[2][0] + C[0][2]) + a.rho0 * (u2x + u2y) - R(2.0 / 3.0) * drho;
+    const R f4 = (C[2][0] - C[0][2]) + a.rho0 * (u2x - u2y);
+    const R f5 = C[1][1] + a.rho0 * vx * vy;
+    const R dxjx = R(-0.75) * (r.w3 * f3 + r.w4 * f4);
+    const R dyjy = R(-0.75) * (r.w3 * f3 - r.w4 * f4);
+    const R shear = R(-3) * r.w5 * f5;
+    if (sxx) sxx[c] = dxjx * inv;
+    if (syy) syy[c] = dyjy * inv;
+    if (sxy) sxy[c] = R(0.5) * shear * inv;
+  }
+}
+
+// Per-block FP64 partial sums of (rho - rho0, rho ux, rho uy, rho |u|^2 / 2).
+// Fixed grid and fixed reduction tree: the result does not depend on timing.
+template <typename S>
+__global__ __launch_bounds__(256) void k_diag_partial(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                                      double* __restrict__ partial) {
+  using R = typename Codec<S>::R;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t n = (int64_t)a.g.nx * a.g.ny;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
+    const int y = (int)(c / a.g.nx), x = (int)(c - (int64_t)y * a.g.nx);
+    R d[9];
+    gather<S, R>(a.g, a.wadd, src, x, y, d);
+    R Fx, Fy;
+    node_force(a, x, y, Fx, Fy);
+    R M[3][3], drho, inv, vx, vy;
+    raw_moments(d, M);
+    node_fields(rates(a), M, Fx, Fy, drho, inv, vx, vy);
+    const double rh = (double)a.rho0 + (double)drho;
+    acc[0] += (double)drho;
+    acc[1] += rh * (double)vx;
+    acc[2] += rh * (double)vy;
+    acc[3] += 0.5 * rh * ((double)vx * (double)vx + (double)vy * (double)vy);
+  }
+  __shared__ double red[4][256];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[(int64_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partial, int nblocks,
+                                                    double base_mass, double* __restrict__ out) {
+  __shared__ double red[4][256];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = (int)threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += partial[(int64_t)b * 4 + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = base_mass + red[0][0];
+    out[1] = red[1][0];
+    out[2] = red[2][0];
+    out[3] = red[3][0];
+  }
+}
+
+// Adjoint of one step: mu_out = J^T mu_in, grad_force += dL/dF.
+template <typename S>
+__global__ __launch_bounds__(256) void k_adjoint_step(KArgs<typename Codec<S>::R> a, const S* __restrict__ prev,
+                                                      const typename Codec<S>::R* __restrict__ mu_in,
+                                                      typename Codec<S>::R* __restrict__ mu_out,
+                                                      typename Codec<S>::R* __restrict__ grad_force) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  R d[9];
+  gather<S, R>(a.g, a.wadd, prev, p.x, p.y, d);
+  R Fx, Fy;
+  node_force(a, p.x, p.y, Fx, Fy);
+  const Rates<R> r = rates(a);
+  R out[9];
+  NodeFwd<R> s;
+  collide(r, Fx, Fy, d, out, s);
+  const int64_t c = (int64_t)p.y * a.g.pitch + p.x;
+  R mu[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * a.g.plane + c];
+  R nu[9], aFx = R(0), aFy = R(0);
+  collide_T(r, s, mu, nu, aFx, aFy);
+  // Reverse streaming: the transpose of the gather permutation.
+  scatter<R, R>(a.g, a.wadd, mu_out, p.x, p.y, nu, false);
+  if (grad_force) {
+    const int64_t cf = (int64_t)p.y * a.g.nx + p.x;
+    grad_force[cf] += aFx;
+    grad_force[(int64_t)a.g.nx * a.g.ny + cf] += aFy;
+  }
+}
+
+// Adjoint of the macroscopic map rho, u at lattice lat.
+template <typename S>
+__global__ __launch_bounds__(256) void k_adjoint_macro(KArgs<typename Codec<S>::R> a, const S* __restrict__ lat,
+                                                       const typename Codec<S>::R* g_rho,
+                                                       const typename Codec<S>::R* g_ux,
+                                                       const typename Codec<S>::R* g_uy,
+                                                       typename Codec<S>::R* __restrict__ mu_out,
+                                                       typename Codec<S>::R* __restrict__ grad_force) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  R d[9];
+  gather<S, R>(a.g, a.wadd, lat, p.x, p.y, d);
+  R Fx, Fy;
+  node_force(a, p.x, p.y, Fx, Fy);
+  R M[3][3], drho, inv, vx, vy;
+  raw_moments(d, M);
+  node_fields(rates(a), M, Fx, Fy, drho, inv, vx, vy);
+  const int64_t cf = (int64_t)p.y * a.g.nx + p.x;
+  const R gr = g_rho ? g_rho[cf] : R(0);
+  const R gx = g_ux ? g_ux[cf] : R(0);
+  const R gy = g_uy ? g_uy[cf] : R(0);
+  // d rho / d f_a = 1;  d u / d f_a = (e_a - u)/rho;  d u / d F = 1/(2 rho).
+  R nu[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    nu[k] = gr + (gx * (R(EX[k]) - vx) + gy * (R(EY[k]) - vy)) * inv;
+  scatter<R, R>(a.g, a.wadd, mu_out, p.x, p.y, nu, false);
+  if (grad_force) {
+    grad_force[cf] += R(0.5) * gx * inv;
+    grad_force[(int64_t)a.g.nx * a.g.ny + cf] += R(0.5) * gy * inv;
+  }
+}
+
+// Adjoint of the initial state map (rho, u, F) -> lattice.
+template <typename S>
+__global__ __launch_bounds__(256) void k_adjoint_init(KArgs<typename Codec<S>::R> a,
+                                                      const double* rho, const double* ux,
+                                                      const double* uy,
+                                                      const typename Codec<S>::R* __restrict__ mu0,
+                                                      typename Codec<S>::R* g_rho,
+                                                      typename Codec<S>::R* g_ux,
+                                                      typename Codec<S>::R* g_uy,
+                                                      typename Codec<S>::R* __restrict__ grad_force) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  const int64_t cf = (int64_t)p.y * a.g.nx + p.x;
+  // The initial lattice is the scatter of v(x); its cotangent w.r.t. v is the
+  // gather of mu0 (no wall term: it is additive).
+  R av[9];
+  {
+    const Edges e = edges(a.g, p.x, p.y);
+    R add;
+#define LBM_GATHER_MU(A) av[A] = mu0[link_src<A, R>(a.g, e, p.x, p.y, a.wadd, add)];
+    LBM_GATHER_MU(0) LBM_GATHER_MU(1) LBM_GATHER_MU(2) LBM_GATHER_MU(3) LBM_GATHER_MU(4)
+    LBM_GATHER_MU(5) LBM_GATHER_MU(6) LBM_GATHER_MU(7) LBM_GATHER_MU(8)
+#undef LBM_GATHER_MU
+  }
+  R Fx, Fy;
+  node_force(a, p.x, p.y, Fx, Fy);
+  const R vx = (R)ux[cf], vy = (R)uy[cf];
+  R Cs[3][3], Y[3][3], v[9];
+  equilibrium_cm(a.rho0, (R)(rho[cf] - (double)a.rho0), vx, vy, R(-0.5) * Fx, R(-0.5) * Fy, Cs);
+  populations(vx, vy, Cs, Y, v);
+  R aCs[3][3], aux = R(0), auy = R(0), adrho = R(0), ahx = R(0), ahy = R(0);
+  populations_T(vx, vy, Cs, Y, av, aCs, aux, auy);
+  equilibrium_cm_T(a.rho0, vx, vy, aCs, adrho, aux, auy, ahx, ahy);
+  if (g_rho) g_rho[cf] = adrho;
+  if (g_ux) g_ux[cf] = aux;
+  if (g_uy) g_uy[cf] = auy;
+  if (grad_force) {
+    grad_force[cf] += R(-0.5) * ahx;
+    grad_force[(int64_t)a.g.nx * a.g.ny + cf] += R(-0.5) * ahy;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static dim3 grid_of(const Geom& g) { return dim3((unsigned)(g.tiles_x * g.tiles_y)); }
+
+#define LBM_DISPATCH(storage, CALL)                                 \
+  switch (storage) {                                                \
+    case 0: { using S = double; CALL; }                             \
+    case 1: { using S = float; CALL; }                              \
+    case 2: { using S = _Float16; CALL; }                           \
+    case 3: { using S = __bf16; CALL; }                             \
+    default: return hipErrorInvalidValue;                           \
+  }
+
+// The KArgs arrive as the double or float instantiation; the dispatcher
+// picks the one matching the storage mode's compute real.
+template <typename S>
+static const KArgs<typename Codec<S>::R>& args_of(const KArgsAny& a) {
+  if constexpr (sizeof(typename Codec<S>::R) == 8) return a.d; else return a.f;
+}
+
+hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, hipStream_t st) {
+  LBM_DISPATCH(a.storage, {
+    hipLaunchKernelGGL(k_step<S>, grid_of(a.g()), dim3(256), 0, st, args_of<S>(a), (const S*)src, (S*)dst);
+    return hipGetLastError();
+  })
+}
+
+hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
+                       hipStream_t st) {
+  LBM_DISPATCH(a.storage, {
+    hipLaunchKernelGGL(k_init<S>, grid_of(a.g()), dim3(256), 0, st, args_of<S>(a), (const double*)rho,
+                       (const double*)ux, (const double*)uy, (S*)dst);
+    return hipGetLastError();
+  })
+}
+
+hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st) {
+  LBM_DISPATCH(a.storage, {
+    hipLaunchKernelGGL(k_set<S>, grid_of(a.g()), dim3(256), 0, st, args_of<S>(a), (const double*)f, (S*)dst);
+    return hipGetLastError();
+  })
+}
+
+hipError_t launch_get(const KArgsAny& a, const void* src, void* f, hipStream_t st) {
+  LBM_DISPATCH(a.storage, {
+    hipLaunchKernelGGL(k_get<S>, grid_of(a.g()), dim3(256), 0, st, args_of<S>(a), (const S*)src, (double*)f);
+    return hipGetLastError();
+  })
+}
+
+hipError_t launch_macro(const KArgsAny& a, const void* src, void* rho, void* ux, void* uy, void* sxx,
+                        void* syy, void* sxy, hipStream_t st) {
+  LBM_DISPATCH(a.storage, {
+    hipLaunchKernelGGL(k_macro<S>, grid_of(a.g()), dim3(256), 0, st, args_of<S>(a), (const S*)src,
+                       (double*)rho, (double*)ux, (double*)uy, (double*)sxx, (double*)syy, (double*)sxy);
+    return hipGetLastError();
+  })
+}
+
+hipError_t launch_diag(const KArgsAny& a, const void* src, double* partial, int nblocks, double base_mass,
+                       double* out, hipStream_t st) {
+  LBM_DISPATCH(a.storage, {
+    hipLaunchKernelGGL(k_diag_partial<S>, dim3((unsigned)nblocks), dim3(256), 0, st, args_of<S>(a),
+                       (const S*)src, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, (const double*)partial, nblocks,
+                       base_mass, out);
+    return hipGetLastError();
+  })
+}
+
+hipError_t launch_adjoint_step(const KArgsAny& a, const void* prev, const void* mu_in, void* mu_out,
+                               void* grad_force, hipStream_t st) {
+  switch (a.storage) {
+    case 0:
+      hipLaunchKernelGGL(k_adjoint_step<double>, grid_of(a.g()), dim3(256), 0, st, a.d, (const double*)prev,
+                         (const double*)mu_in, (double*)mu_out, (double*)grad_force);
+      return hipGetLastError();
+    case 1:
+      hipLaunchKernelGGL(k_adjoint_step<float>, grid_of(a.g()), dim3(256), 0, st, a.f, (const float*)prev,
+                         (const float*)mu_in, (float*)mu_out, (float*)grad_force);
+      return hipGetLastError();
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adjoint_macro(const KArgsAny& a, const void* lat, const void* g_rho, const void* g_ux,
+                                const void* g_uy, void* mu_out, void* grad_force, hipStream_t st) {
+  switch (a.storage) {
+    case 0:
+      hipLaunchKernelGGL(k_adjoint_macro<double>, grid_of(a.g()), dim3(256), 0, st, a.d, (const double*)lat,
+                         (const double*)g_rho, (const double*)g_ux, (const double*)g_uy, (double*)mu_out,
+                         (double*)grad_force);
+      return hipGetLastError();
+    case 1:
+      hipLaunchKernelGGL(k_adjoint_macro<float>, grid_of(a.g()), dim3(256), 0, st, a.f, (const float*)lat,
+                         (const float*)g_rho, (const float*)g_ux, (const float*)g_uy, (float*)mu_out,
+                         (float*)grad_force);
+      return hipGetLastError();
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adjoint_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy,
+                               const void* mu0, void* g_rho, void* g_ux, void* g_uy, void* grad_force,
+                               hipStream_t st) {
+  switch (a.storage) {
+    case 0:
+      hipLaunchKernelGGL(k_adjoint_init<double>, grid_of(a.g()), dim3(256), 0, st, a.d, (const double*)rho,
+                         (const double*)ux, (const double*)uy, (const double*)mu0, (double*)g_rho,
+                         (double*)g_ux, (double*)g_uy, (double*)grad_force);
+      return hipGetLastError();
+    case 1:
+      hipLaunchKernelGGL(k_adjoint_init<float>, grid_of(a.g()), dim3(256), 0, st, a.f, (const double*)rho,
+                         (const double*)ux, (const double*)uy, (const float*)mu0, (float*)g_rho,
+                         (float*)g_ux, (float*)g_uy, (float*)grad_force);
+      return hipGetLastError();
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,54 @@
+// lbm_launch.h -- internal interface between the host API (lbm_api.hip) and
+// the kernels (lbm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Lattice geometry and launch tiling.
+struct Geom {
+  int32_t nx, ny;
+  int32_t pitch;     // elements per row (multiple of 64)
+  int64_t plane;     // ny * pitch
+  int32_t tx_shift;  // log2 of the tile width TX (tiles are TX x 256/TX nodes)
+  int32_t tiles_x, tiles_y;
+  int32_t wall[4];   // x_lo, x_hi, y_lo, y_hi: 1 = wall, 0 = periodic
+};
+
+// Kernel arguments in the compute real R.
+template <typename R>
+struct KArgs {
+  Geom g;
+  R w[6];          // omega_3 .. omega_8
+  R rho0, fx, fy;
+  const R* force;  // [2][ny][nx] or nullptr
+  R wadd[4 * 9];   // moving-wall term per side and direction
+};
+
+struct KArgsAny {
+  int32_t storage;  // lbm_storage
+  KArgs<double> d;  // used when the compute real is double (FP64)
+  KArgs<float> f;   // used otherwise
+  const Geom& g() const { return storage == 0 ? d.g : f.g; }
+};
+
+hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, hipStream_t st);
+hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
+                       hipStream_t st);
+hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);
+hipError_t launch_get(const KArgsAny& a, const void* src, void* f, hipStream_t st);
+hipError_t launch_macro(const KArgsAny& a, const void* src, void* rho, void* ux, void* uy, void* sxx,
+                        void* syy, void* sxy, hipStream_t st);
+hipError_t launch_diag(const KArgsAny& a, const void* src, double* partial, int nblocks, double base_mass,
+                       double* out, hipStream_t st);
+hipError_t launch_adjoint_step(const KArgsAny& a, const void* prev, const void* mu_in, void* mu_out,
+                               void* grad_force, hipStream_t st);
+hipError_t launch_adjoint_macro(const KArgsAny& a, const void* lat, const void* g_rho, const void* g_ux,
+                                const void* g_uy, void* mu_out, void* grad_force, hipStream_t st);
+hipError_t launch_adjoint_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy,
+                               const void* mu0, void* g_rho, void* g_ux, void* g_uy, void* grad_force,
+                               hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/lbm.h declares, and rejects bad parameters before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("lbm_create", "lbm_step", "lbm_macroscopic", "lbm_adjoint_step", "lbm_diagnostics",
+              "lbm_init_equilibrium", "lbm_destroy", "lbm_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1202_6351_amd import _lib
+    lib = _lib.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def _params(**kw):
+    from paper_1202_6351_amd import Params
+    base = dict(nx=100, ny=37, tau=0.8, storage="fp32")
+    base.update(kw)
+    return Params(**base)
+
+
+def test_layout_pitch_and_bytes():
+    from paper_1202_6351_amd import lattice_layout
+    for storage, sz in (("fp64", 8), ("fp32", 4), ("fp16", 2), ("bf16", 2)):
+        pitch, nbytes = lattice_layout(_params(storage=storage))
+        assert pitch == 128 and nbytes == 9 * 37 * 128 * sz
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=0.4), "omega_nu"),
+    (dict(omega3=2.0), "omega3"),
+    (dict(nx=1), "grid"),
+    (dict(bc=("periodic", "wall", "periodic", "periodic")), "periodic on one side"),
+    (dict(wall_u=(0.0, 0.0, 0.1, 0.0)), "periodic side"),
+    (dict(rho0=0.0), "rho0"),
+])
+def test_invalid_parameters_rejected(kw, msg):
+    from paper_1202_6351_amd import _lib, lattice_layout
+    with pytest.raises(_lib.LbmError) as ei:
+        lattice_layout(_params(**kw))
+    assert ei.value.status == _lib.LBM_EINVAL and msg in str(ei.value)
+
+
+def test_create_rejects_null_and_misaligned_buffers():
+    from paper_1202_6351_amd import _lib
+    lib = _lib.lib()
+    cp = _params().c()
+    ctx = ctypes.c_void_p()
+    st = lib.lbm_create(ctypes.byref(cp), None, None, None, None, ctypes.byref(ctx))
+    assert st == _lib.LBM_EINVAL and not ctx.value
+    assert b"lattice buffers" in lib.lbm_last_error(None)
+    st = lib.lbm_create(ctypes.byref(cp), ctypes.c_void_p(0x1000 + 8), ctypes.c_void_p(0x20000),
+                        None, None, ctypes.byref(ctx))
+    assert st == _lib.LBM_EINVAL and b"aligned" in lib.lbm_last_error(None)

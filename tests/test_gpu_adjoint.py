@@ -1,0 +1,293 @@
+"""GPU checks of the hand-written adjoint (through the C ABI).
+
+* per-step dot-product tests <J v, w> = <v, J^T w> with J v from central
+  finite differences of the forward step (FP64);
+* the macroscopic and initial-state adjoints the same way;
+* full checkpointed rollouts: directional central differences on 32x32, and
+  agreement with float64 torch autograd of the independent dense-matrix
+  formulation in oracle/ref_torch.py on 16x16.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ref_torch
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+BCMAP = {"periodic": 0, "wall": 1}
+
+BCS = [
+    (("periodic",) * 4, (0, 0, 0, 0)),
+    (("periodic", "periodic", "wall", "wall"), (0, 0, 0.0, 0.1)),
+    (("wall",) * 4, (0.01, -0.02, 0.03, 0.1)),
+]
+
+
+def _lattice(nx, ny, force, storage="fp64", **kw):
+    from paper_1202_6351_amd import Lattice, Params
+    return Lattice(Params(nx, ny, storage=storage, **kw), device=DEV,
+                   force=torch.from_numpy(force))
+
+
+def _lattice_noise(lat, seed):
+    """Random lattice-layout tensor, zero in the row padding."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    ny, nx, pitch = lat.params.ny, lat.params.nx, lat.pitch
+    v = torch.zeros(9, ny, pitch, dtype=torch.float64)
+    v[:, :, :nx] = torch.randn(9, ny, nx, generator=g, dtype=torch.float64)
+    return v.reshape(-1).to(DEV)
+
+
+def _step(lat, src):
+    out = torch.zeros_like(src)
+    lat.step_between(src, out)
+    return out
+
+
+@pytest.mark.parametrize("bci", range(len(BCS)))
+@pytest.mark.parametrize("shape", [(16, 12), (67, 33)])
+def test_step_adjoint_dot_product(bci, shape):
+    nx, ny = shape
+    bc, wu = BCS[bci]
+    frc = W.force_field(nx, ny, 1e-3, seed=5)
+    lat = _lattice(nx, ny, frc, tau=0.6, omega3=1.2, omega6=0.8, omega7=1.4, omega8=1.1,
+                   bc=bc, wall_u=wu)
+    lat.set_populations(W.random_populations(nx, ny, seed=9))
+    L = lat.current.clone()
+    v, w = _lattice_noise(lat, 1), _lattice_noise(lat, 2)
+    eps = 1e-6
+    jv = (_step(lat, L + eps * v) - _step(lat, L - eps * v)) / (2 * eps)
+    mu_out = torch.zeros_like(w)
+    gF = torch.zeros_like(lat.force)
+    lat.adjoint_step(L, w, mu_out, gF)
+    lhs, rhs = torch.dot(jv, w).item(), torch.dot(v, mu_out).item()
+    assert abs(lhs - rhs) <= 1e-8 * abs(lhs), (lhs, rhs)
+    # force direction
+    dF = torch.randn(lat.force.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(3)).to(DEV)
+    f0 = lat.force.clone()
+    lat.force.copy_(f0 + eps * dF)
+    up = _step(lat, L)
+    lat.force.copy_(f0 - eps * dF)
+    dn = _step(lat, L)
+    lat.force.copy_(f0)
+    lhs = torch.dot((up - dn) / (2 * eps), w).item()
+    rhs = torch.dot(dF.reshape(-1), gF.reshape(-1)).item()
+    assert abs(lhs - rhs) <= 1e-8 * abs(lhs), (lhs, rhs)
+
+
+def test_step_adjoint_support():
+    """With w nonzero on one element of the new lattice (node x, direction
+    a), J^T w is supported exactly on the nine elements of the old lattice
+    that stream into node x."""
+    nx, ny = 8, 6
+    frc = np.zeros((2, ny, nx))
+    lat = _lattice(nx, ny, frc, tau=1.0)
+    lat.init_equilibrium(*W.at_rest(nx, ny))
+    L = lat.current.clone()
+    w = torch.zeros_like(L)
+    pitch = lat.pitch
+    a, y, x = 5, 2, 3
+    w[(a * ny + y) * pitch + x] = 1.0
+    mu_out = torch.zeros_like(w)
+    lat.adjoint_step(L, w, mu_out, None)
+    nz = torch.nonzero(mu_out.reshape(9, ny, pitch)).cpu().numpy()
+    # the node's populations all stream in from its 9 neighbours (x - e_a)
+    ex = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    allowed = {(b, (y - ey[b]) % ny, (x - ex[b]) % nx) for b in range(9)}
+    assert {tuple(r) for r in nz} <= allowed and len(nz) > 0
+
+
+def test_macroscopic_adjoint():
+    nx, ny = 20, 14
+    bc, wu = BCS[2]
+    frc = W.force_field(nx, ny, 1e-3, seed=6)
+    lat = _lattice(nx, ny, frc, tau=0.7, bc=bc, wall_u=wu)
+    lat.set_populations(W.random_populations(nx, ny, seed=4))
+    L = lat.current.clone()
+    g = torch.Generator().manual_seed(8)
+    gr, gx, gy = (torch.randn(ny, nx, dtype=torch.float64, generator=g).to(DEV) for _ in range(3))
+
+    def J(buf):
+        lat.restore(buf, 0)
+        m = lat.macroscopic(strain=False)
+        return (gr * m["rho"] + gx * m["ux"] + gy * m["uy"]).sum().item()
+
+    v = _lattice_noise(lat, 3)
+    eps = 1e-6
+    fd = (J(L + eps * v) - J(L - eps * v)) / (2 * eps)
+    mu = torch.zeros_like(L)
+    gF = torch.zeros_like(lat.force)
+    lat.adjoint_macroscopic(L, gr, gx, gy, mu, gF)
+    assert abs(fd - torch.dot(v, mu).item()) <= 1e-8 * abs(fd)
+    dF = torch.randn(lat.force.shape, dtype=torch.float64, generator=g).to(DEV)
+    f0 = lat.force.clone()
+    lat.force.copy_(f0 + eps * dF)
+    up = J(L)
+    lat.force.copy_(f0 - eps * dF)
+    dn = J(L)
+    lat.force.copy_(f0)
+    fd = (up - dn) / (2 * eps)
+    assert abs(fd - torch.dot(dF.reshape(-1), gF.reshape(-1)).item()) <= 1e-8 * abs(fd)
+
+
+def test_init_adjoint():
+    nx, ny = 18, 10
+    bc, wu = BCS[1]
+    frc = W.force_field(nx, ny, 1e-3, seed=2)
+    lat = _lattice(nx, ny, frc, tau=0.7, bc=bc, wall_u=wu)
+    rho, ux, uy = (torch.from_numpy(a).to(DEV) for a in W.random_flow(nx, ny, seed=3))
+    w = _lattice_noise(lat, 5)
+
+    def J(r, vx, vy):
+        lat.init_equilibrium(r, vx, vy)
+        return torch.dot(lat.current, w).item()
+
+    gr, gx, gy = (torch.empty_like(rho) for _ in range(3))
+    gF = torch.zeros_like(lat.force)
+    lat.adjoint_init(rho, ux, uy, w, gr, gx, gy, gF)
+    g = torch.Generator().manual_seed(1)
+    eps = 1e-6
+    for k, grad in ((0, gr), (1, gx), (2, gy)):
+        d = torch.randn(ny, nx, dtype=torch.float64, generator=g).to(DEV)
+        args_p = [rho, ux, uy]
+        args_m = [rho, ux, uy]
+        args_p = [a + eps * d if i == k else a for i, a in enumerate(args_p)]
+        args_m = [a - eps * d if i == k else a for i, a in enumerate(args_m)]
+        fd = (J(*args_p) - J(*args_m)) / (2 * eps)
+        assert abs(fd - torch.dot(d.reshape(-1), grad.reshape(-1)).item()) <= 1e-8 * abs(fd)
+    dF = torch.randn(lat.force.shape, dtype=torch.float64, generator=g).to(DEV)
+    f0 = lat.force.clone()
+    lat.force.copy_(f0 + eps * dF)
+    up = J(rho, ux, uy)
+    lat.force.copy_(f0 - eps * dF)
+    dn = J(rho, ux, uy)
+    lat.force.copy_(f0)
+    fd = (up - dn) / (2 * eps)
+    assert abs(fd - torch.dot(dF.reshape(-1), gF.reshape(-1)).item()) <= 1e-8 * abs(fd)
+
+
+# ------------------------------------------------------------------ rollouts
+
+def _tg_target(n, t, tau, u0=0.02):
+    """Analytic Taylor-Green velocity at time t (the flow-matching target)."""
+    import math
+    k = 2 * math.pi / n
+    nu = (tau - 0.5) / 3
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    dec = math.exp(-2 * nu * k * k * t)
+    return np.stack([-u0 * np.cos(k * x) * np.sin(k * y) * dec, u0 * np.sin(k * x) * np.cos(k * y) * dec])
+
+
+def _loss_fn(target):
+    def loss(u):
+        return ((u - target) ** 2).sum(dim=0).mean()
+    return loss
+
+
+def test_rollout_finite_differences_32():
+    """32x32 periodic FP64, learnable force field (N(0, 1e-6^2), seed 4) and
+    initial velocity (0), Taylor-Green target at U0 = 0.02, T = 200 with a
+    checkpoint every 50 steps: directional central differences."""
+    from paper_1202_6351_amd import Params, rollout
+    n, tau, T = 32, 0.8, 200
+    p = Params(n, n, tau=tau, storage="fp64")
+    target = torch.from_numpy(_tg_target(n, T, tau)).to(DEV)
+    loss = _loss_fn(target)
+    F = torch.from_numpy(W.force_field(n, n, 1e-6, seed=4)).to(DEV).requires_grad_(True)
+    u0 = torch.zeros(2, n, n, dtype=torch.float64, device=DEV, requires_grad=True)
+    _, u = rollout(p, F, u0, T, checkpoint_every=50)
+    loss(u).backward()
+    gF, gu0 = F.grad.clone(), u0.grad.clone()
+    gen = torch.Generator().manual_seed(12)
+
+    def L(Fv, uv):
+        with torch.no_grad():
+            return loss(rollout(p, Fv, uv, T, checkpoint_every=50)[1]).item()
+
+    for which in ("F", "u0"):
+        d = torch.randn(2, n, n, dtype=torch.float64, generator=gen).to(DEV)
+        eps = 1e-8 if which == "F" else 1e-6
+        if which == "F":
+            fd = (L(F.detach() + eps * d, u0.detach()) - L(F.detach() - eps * d, u0.detach())) / (2 * eps)
+            an = torch.dot(d.reshape(-1), gF.reshape(-1)).item()
+        else:
+            fd = (L(F.detach(), u0.detach() + eps * d) - L(F.detach(), u0.detach() - eps * d)) / (2 * eps)
+            an = torch.dot(d.reshape(-1), gu0.reshape(-1)).item()
+        print(f"rollout FD {which}: fd {fd:.10e} adjoint {an:.10e}")
+        assert abs(fd - an) <= 1e-6 * abs(fd)
+    # 20 random single entries of dL/dF
+    idx = torch.randint(0, 2 * n * n, (20,), generator=gen)
+    for i in idx.tolist():
+        e = torch.zeros(2 * n * n, dtype=torch.float64, device=DEV)
+        e[i] = 1.0
+        e = e.reshape(2, n, n)
+        eps = 1e-7
+        fd = (L(F.detach() + eps * e, u0.detach()) - L(F.detach() - eps * e, u0.detach())) / (2 * eps)
+        an = gF.reshape(-1)[i].item()
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-12 * gF.abs().max().item(), (i, fd, an)
+
+
+@pytest.mark.parametrize("bci", range(len(BCS)))
+def test_rollout_matches_torch_autograd(bci):
+    """16x14 FP64 rollout, T = 30 (checkpoint every 7): gradients equal float64
+    torch autograd of the independent dense-matrix step."""
+    from paper_1202_6351_amd import Params, rollout
+    nx, ny, tau, T = 16, 14, 0.7, 30
+    bc, wu = BCS[bci]
+    kw = dict(tau=tau, omega3=1.1, omega6=0.9, omega7=1.2, omega8=1.3, bc=bc, wall_u=wu)
+    p = Params(nx, ny, storage="fp64", **kw)
+    Fn = W.force_field(nx, ny, 1e-4, seed=7)
+    rho_n, ux_n, uy_n = W.random_flow(nx, ny, seed=2, u_amp=0.03, rho_amp=0.0)
+    tgt = np.stack(W.random_flow(nx, ny, seed=3, u_amp=0.03)[1:])
+    F = torch.from_numpy(Fn).to(DEV).requires_grad_(True)
+    u0 = torch.from_numpy(np.stack([ux_n, uy_n])).to(DEV).requires_grad_(True)
+    rho_T, u = rollout(p, F, u0, T, checkpoint_every=7)
+    target = torch.from_numpy(tgt).to(DEV)
+    L = ((u - target) ** 2).sum(dim=0).mean() + 0.3 * (rho_T ** 2).mean()
+    L.backward()
+
+    # reference: torch autograd on the CPU
+    Ft = torch.from_numpy(Fn.reshape(2, -1).T.copy()).requires_grad_(True)
+    u0t = torch.from_numpy(np.stack([ux_n, uy_n]).reshape(2, -1)).requires_grad_(True)
+    tab = ref_torch.stream_tables(nx, ny, [BCMAP[b] for b in bc], wu)
+    om = p.c()
+    omega = [0, 0, 0, om.omega3, om.omega_nu, om.omega_nu, om.omega6, om.omega7, om.omega8]
+    f = ref_torch.init_state(torch.ones(nx * ny, dtype=torch.float64), u0t[0], u0t[1], Ft)
+    for _ in range(T):
+        f = ref_torch.step(f, Ft, omega, tab)
+    r, vx, vy = ref_torch.velocity(f, Ft)
+    tt = torch.from_numpy(tgt.reshape(2, -1))
+    Lr = ((vx - tt[0]) ** 2 + (vy - tt[1]) ** 2).mean() + 0.3 * (r ** 2).mean()
+    Lr.backward()
+    assert abs(L.item() - Lr.item()) <= 1e-12 * abs(Lr.item())
+    gF_ref = Ft.grad.T.reshape(2, ny, nx).numpy()
+    gu_ref = u0t.grad.reshape(2, ny, nx).numpy()
+    gF, gu = F.grad.cpu().numpy(), u0.grad.cpu().numpy()
+    assert np.abs(gF - gF_ref).max() <= 1e-10 * np.abs(gF_ref).max()
+    assert np.abs(gu - gu_ref).max() <= 1e-10 * np.abs(gu_ref).max()
+
+
+def test_rollout_fp32_gradient_close_to_fp64():
+    """The FP32 adjoint agrees with the FP64 one to FP32 accuracy (64x64,
+    T = 300, checkpoint every 100)."""
+    from paper_1202_6351_amd import Params, rollout
+    n, tau, T = 64, 0.8, 300
+    target = _tg_target(n, T, tau)
+    grads = {}
+    for storage in ("fp64", "fp32"):
+        real = torch.float64 if storage == "fp64" else torch.float32
+        p = Params(n, n, tau=tau, storage=storage)
+        F = torch.from_numpy(W.force_field(n, n, 1e-6, seed=4)).to(DEV, real).requires_grad_(True)
+        u0 = torch.zeros(2, n, n, dtype=real, device=DEV, requires_grad=True)
+        _, u = rollout(p, F, u0, T, checkpoint_every=100)
+        ((u - torch.from_numpy(target).to(DEV)) ** 2).sum(dim=0).mean().backward()
+        grads[storage] = (F.grad.double().cpu().numpy(), u0.grad.double().cpu().numpy())
+    for k in range(2):
+        a, b = grads["fp32"][k], grads["fp64"][k]
+        rel = np.abs(a - b).sum() / np.abs(b).sum()
+        print(f"fp32 vs fp64 gradient {k}: rel {rel:.3e}")
+        assert rel < 1e-4
