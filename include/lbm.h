@@ -78,7 +78,8 @@ typedef enum {
 
 /* Problem statement of one lattice (Sec. II and III).
  *   nx, ny      fluid nodes; a wall sits half a spacing outside the first /
- *               last node (2 <= nx, ny; ny * pitch < 2^31).
+ *               last node (2 <= nx, ny; one plane, ny * pitch elements of
+ *               the storage type, below 4 GiB).
  *   omega_nu    shear rate omega_4 = omega_5 = 1/tau, in (0, 2); kinematic
  *               viscosity nu = (1/omega_nu - 1/2)/3 (Sec. II).
  *   omega3      bulk rate omega_3; omega6, omega7, omega8 the third- and

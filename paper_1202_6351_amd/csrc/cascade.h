@@ -41,6 +41,10 @@
 
 #include <hip/hip_runtime.h>
 
+// Every per-node function is host-callable too, so the arithmetic can be
+// unit-tested on the CPU (FP64 instantiation) against the reference.
+#define LBM_HD __host__ __device__ __forceinline__
+
 namespace lbm {
 
 // Direction order of Section II.  DIR[J][I] is the direction with
@@ -70,40 +74,40 @@ struct NodeFwd {
 // ------------------------------------------------------ 3-point operators
 // Moments of (p-, p0, p+) on {-1, 0, +1}: m0 = sum, m1 = p+ - p-, m2 = p+ + p-.
 template <typename R>
-__device__ __forceinline__ void ax_mom(R pm, R p0, R pp, R& m0, R& m1, R& m2) {
+LBM_HD void ax_mom(R pm, R p0, R pp, R& m0, R& m1, R& m2) {
   m2 = pp + pm;
   m1 = pp - pm;
   m0 = m2 + p0;
 }
 template <typename R>
-__device__ __forceinline__ void ax_mom_T(R a0, R a1, R a2, R& apm, R& ap0, R& app) {
+LBM_HD void ax_mom_T(R a0, R a1, R a2, R& apm, R& ap0, R& app) {
   ap0 = a0;
   apm = a0 - a1 + a2;
   app = a0 + a1 + a2;
 }
 // Inverse: p0 = m0 - m2, p-+ = (m2 -+ m1)/2.
 template <typename R>
-__device__ __forceinline__ void ax_inv(R m0, R m1, R m2, R& pm, R& p0, R& pp) {
+LBM_HD void ax_inv(R m0, R m1, R m2, R& pm, R& p0, R& pp) {
   p0 = m0 - m2;
   pm = R(0.5) * (m2 - m1);
   pp = R(0.5) * (m2 + m1);
 }
 template <typename R>
-__device__ __forceinline__ void ax_inv_T(R apm, R ap0, R app, R& a0, R& a1, R& a2) {
+LBM_HD void ax_inv_T(R apm, R ap0, R app, R& a0, R& a1, R& a2) {
   a0 = ap0;
   a1 = R(0.5) * (app - apm);
   a2 = R(0.5) * (app + apm) - ap0;
 }
 // Shift raw -> central about u: c1 = m1 - u m0, c2 = m2 - 2u m1 + u^2 m0.
 template <typename R>
-__device__ __forceinline__ void ax_ctr(R u, R m0, R m1, R m2, R& c0, R& c1, R& c2) {
+LBM_HD void ax_ctr(R u, R m0, R m1, R m2, R& c0, R& c1, R& c2) {
   c0 = m0;
   c1 = m1 - u * m0;
   c2 = m2 - u * (m1 + c1);
 }
 // Transpose of ax_ctr at inputs (m0, m1, m2); accumulates d/du into au.
 template <typename R>
-__device__ __forceinline__ void ax_ctr_T(R u, R m0, R m1, R a0, R a1, R a2,
+LBM_HD void ax_ctr_T(R u, R m0, R m1, R a0, R a1, R a2,
                                          R& am0, R& am1, R& am2, R& au) {
   const R c1 = m1 - u * m0;
   am2 = a2;
@@ -113,13 +117,13 @@ __device__ __forceinline__ void ax_ctr_T(R u, R m0, R m1, R a0, R a1, R a2,
 }
 // Shift central -> raw about u: m1 = c1 + u c0, m2 = c2 + 2u c1 + u^2 c0.
 template <typename R>
-__device__ __forceinline__ void ax_unc(R u, R c0, R c1, R c2, R& m0, R& m1, R& m2) {
+LBM_HD void ax_unc(R u, R c0, R c1, R c2, R& m0, R& m1, R& m2) {
   m0 = c0;
   m1 = c1 + u * c0;
   m2 = c2 + u * (c1 + m1);
 }
 template <typename R>
-__device__ __forceinline__ void ax_unc_T(R u, R c0, R c1, R a0, R a1, R a2,
+LBM_HD void ax_unc_T(R u, R c0, R c1, R a0, R a1, R a2,
                                          R& ac0, R& ac1, R& ac2, R& au) {
   const R m1 = c1 + u * c0;
   ac2 = a2;
@@ -134,7 +138,7 @@ __device__ __forceinline__ void ax_unc_T(R u, R c0, R c1, R a0, R a1, R a2,
 // With hF = -F/2 this is f^eq - S/2 (the initial state); its entries of
 // order >= 2 are the relaxation targets of the collision.
 template <typename R>
-__device__ __forceinline__ void equilibrium_cm(R r0, R drho, R ux, R uy, R hFx, R hFy, R Cs[3][3]) {
+LBM_HD void equilibrium_cm(R r0, R drho, R ux, R uy, R hFx, R hFy, R Cs[3][3]) {
   const R ux2 = ux * ux, uy2 = uy * uy;
   Cs[0][0] = drho;
   Cs[1][0] = hFx + r0 * ux;
@@ -148,7 +152,7 @@ __device__ __forceinline__ void equilibrium_cm(R r0, R drho, R ux, R uy, R hFx, 
 }
 
 template <typename R>
-__device__ __forceinline__ void equilibrium_cm_T(R r0, R ux, R uy, const R aCs[3][3], R& adrho,
+LBM_HD void equilibrium_cm_T(R r0, R ux, R uy, const R aCs[3][3], R& adrho,
                                                  R& aux, R& auy, R& ahFx, R& ahFy) {
   const R ux2 = ux * ux, uy2 = uy * uy;
   adrho += aCs[0][0] + R(1.0 / 3.0) * (aCs[2][0] + aCs[0][2]) + R(1.0 / 9.0) * aCs[2][2];
@@ -170,7 +174,7 @@ __device__ __forceinline__ void equilibrium_cm_T(R r0, R ux, R uy, const R aCs[3
 //   Delta C_12 = w7 (E_12 - C_12), Delta C_22 = w8 (E_22 - C_22),
 // E being the equilibrium central moments (deviation form).
 template <typename R>
-__device__ __forceinline__ void relax_delta(const Rates<R>& r, R drho, R ux, R uy, R Fx, R Fy,
+LBM_HD void relax_delta(const Rates<R>& r, R drho, R ux, R uy, R Fx, R Fy,
                                             const R C[3][3], R D[3][3]) {
   R E[3][3];
   equilibrium_cm(r.rho0, drho, ux, uy, R(0), R(0), E);
@@ -190,7 +194,7 @@ __device__ __forceinline__ void relax_delta(const Rates<R>& r, R drho, R ux, R u
 // Reverse of relax_delta: cotangent aD -> aC (C_00, C_10, C_01 get none) and
 // accumulations into adrho, aux, auy, aFx, aFy.
 template <typename R>
-__device__ __forceinline__ void relax_delta_T(const Rates<R>& r, R ux, R uy, const R aD[3][3],
+LBM_HD void relax_delta_T(const Rates<R>& r, R ux, R uy, const R aD[3][3],
                                               R aC[3][3], R& adrho, R& aux, R& auy, R& aFx,
                                               R& aFy) {
   aFx += aD[1][0];
@@ -223,7 +227,7 @@ __device__ __forceinline__ void relax_delta_T(const Rates<R>& r, R ux, R uy, con
 // ------------------------------------------------------------ node passes
 // Raw moments of a node's d (x then y).
 template <typename R>
-__device__ __forceinline__ void raw_moments(const R d[9], R M[3][3]) {
+LBM_HD void raw_moments(const R d[9], R M[3][3]) {
   R A[3][3];  // A[J][m]
 #pragma unroll
   for (int J = 0; J < 3; ++J) ax_mom(d[DIR[J][0]], d[DIR[J][1]], d[DIR[J][2]], A[J][0], A[J][1], A[J][2]);
@@ -234,7 +238,7 @@ __device__ __forceinline__ void raw_moments(const R d[9], R M[3][3]) {
 // Central moments (deviation form) Delta C about u from raw moments M;
 // X receives the intermediate after the x shift.
 template <typename R>
-__device__ __forceinline__ void central(R ux, R uy, const R M[3][3], R X[3][3], R C[3][3]) {
+LBM_HD void central(R ux, R uy, const R M[3][3], R X[3][3], R C[3][3]) {
 #pragma unroll
   for (int n = 0; n < 3; ++n) ax_ctr(ux, M[0][n], M[1][n], M[2][n], X[0][n], X[1][n], X[2][n]);
 #pragma unroll
@@ -245,7 +249,7 @@ __device__ __forceinline__ void central(R ux, R uy, const R M[3][3], R X[3][3], 
 // the intermediate after the y shift.  Linear in Cs: also maps a change of
 // central moments to the change of populations.
 template <typename R>
-__device__ __forceinline__ void populations(R ux, R uy, const R Cs[3][3], R Y[3][3], R out[9]) {
+LBM_HD void populations(R ux, R uy, const R Cs[3][3], R Y[3][3], R out[9]) {
   R Mo[3][3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) ax_unc(uy, Cs[m][0], Cs[m][1], Cs[m][2], Y[m][0], Y[m][1], Y[m][2]);
@@ -262,7 +266,7 @@ __device__ __forceinline__ void populations(R ux, R uy, const R Cs[3][3], R Y[3]
 // Reverse of populations(): cotangent aout of the output -> aCs; accumulates
 // d/du into aux, auy.
 template <typename R>
-__device__ __forceinline__ void populations_T(R ux, R uy, const R Cs[3][3], const R Y[3][3],
+LBM_HD void populations_T(R ux, R uy, const R Cs[3][3], const R Y[3][3],
                                               const R aout[9], R aCs[3][3], R& aux, R& auy) {
   R aB[3][3];
 #pragma unroll
@@ -283,7 +287,7 @@ __device__ __forceinline__ void populations_T(R ux, R uy, const R Cs[3][3], cons
 // Hydrodynamic fields from the raw moments of d (Sec. II): rho = rho0 +
 // M_00, u = (M_10 + F_x/2, M_01 + F_y/2)/rho (the rest part has no momentum).
 template <typename R>
-__device__ __forceinline__ void node_fields(const Rates<R>& r, const R M[3][3], R Fx, R Fy,
+LBM_HD void node_fields(const Rates<R>& r, const R M[3][3], R Fx, R Fy,
                                             R& drho, R& inv_rho, R& ux, R& uy) {
   drho = M[0][0];
   inv_rho = R(1) / (r.rho0 + drho);
@@ -294,7 +298,7 @@ __device__ __forceinline__ void node_fields(const Rates<R>& r, const R M[3][3], 
 // One collision: d (pre-collision deviations) -> out (post-collision), with
 // the intermediates in s.  out = d + T^-1 Sh(+u) Delta C (see header).
 template <typename R>
-__device__ __forceinline__ void collide(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9],
+LBM_HD void collide(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9],
                                         NodeFwd<R>& s) {
   raw_moments(d, s.M);
   node_fields(r, s.M, Fx, Fy, s.drho, s.inv_rho, s.ux, s.uy);
@@ -311,7 +315,7 @@ __device__ __forceinline__ void collide(const Rates<R>& r, R Fx, R Fy, const R d
 // cotangent aout of the output, returns the cotangent ad of d and adds the
 // force cotangent to aFx, aFy.
 template <typename R>
-__device__ __forceinline__ void collide_T(const Rates<R>& r, const NodeFwd<R>& s, const R aout[9],
+LBM_HD void collide_T(const Rates<R>& r, const NodeFwd<R>& s, const R aout[9],
                                           R ad[9], R& aFx, R& aFy) {
   R aux = R(0), auy = R(0), adrho = R(0);
   R aD[3][3];
@@ -344,6 +348,72 @@ __device__ __forceinline__ void collide_T(const Rates<R>& r, const NodeFwd<R>& s
     ad[DIR[J][0]] = aout[DIR[J][0]] + a0;
     ad[DIR[J][1]] = aout[DIR[J][1]] + a1;
     ad[DIR[J][2]] = aout[DIR[J][2]] + a2;
+  }
+}
+
+// Reciprocal: IEEE division in double; for float the hardware estimate
+// refined by one Newton step (error below 1 ulp, a few instructions instead
+// of the correctly rounded division sequence).
+LBM_HD double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return r * __builtin_fmaf(-x, r, 2.0f);
+}
+
+// Shift central -> raw for a column whose zeroth entry is 0.
+template <typename R>
+LBM_HD void ax_unc0(R u, R c1, R c2, R& m0, R& m1, R& m2) {
+  m0 = R(0);
+  m1 = c1;
+  m2 = c2 + R(2) * u * c1;
+}
+
+// The collision of the step kernel: the same function as collide(), written
+// out for Delta C_00 = 0 always and Delta C_10 = Delta C_01 = 0 without a
+// body force, so those zero terms cost no instructions.
+template <typename R, bool kForce>
+LBM_HD void collide_step(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9]) {
+  R M[3][3], X[3][3], C[3][3], D[3][3];
+  raw_moments(d, M);
+  const R drho = M[0][0];
+  const R inv = recip(r.rho0 + drho);
+  const R ux = (kForce ? M[1][0] + R(0.5) * Fx : M[1][0]) * inv;
+  const R uy = (kForce ? M[0][1] + R(0.5) * Fy : M[0][1]) * inv;
+  central(ux, uy, M, X, C);
+  relax_delta(r, drho, ux, uy, Fx, Fy, C, D);
+  // back to raw moments: y shift per m, then x shift per n
+  R Y[3][3], Mo[3][3];
+  if (kForce) {
+    ax_unc0(uy, D[0][1], D[0][2], Y[0][0], Y[0][1], Y[0][2]);
+    ax_unc(uy, D[1][0], D[1][1], D[1][2], Y[1][0], Y[1][1], Y[1][2]);
+  } else {
+    Y[0][0] = R(0);
+    Y[0][1] = R(0);
+    Y[0][2] = D[0][2];
+    ax_unc0(uy, D[1][1], D[1][2], Y[1][0], Y[1][1], Y[1][2]);
+  }
+  ax_unc(uy, D[2][0], D[2][1], D[2][2], Y[2][0], Y[2][1], Y[2][2]);
+  ax_unc0(ux, Y[1][0], Y[2][0], Mo[0][0], Mo[1][0], Mo[2][0]);
+  if (kForce) {
+    ax_unc(ux, Y[0][1], Y[1][1], Y[2][1], Mo[0][1], Mo[1][1], Mo[2][1]);
+  } else {
+    ax_unc0(ux, Y[1][1], Y[2][1], Mo[0][1], Mo[1][1], Mo[2][1]);
+  }
+  ax_unc(ux, Y[0][2], Y[1][2], Y[2][2], Mo[0][2], Mo[1][2], Mo[2][2]);
+  // inverse transform (y then x) and add to d
+  R B[3][3];
+  B[0][0] = R(0.5) * (Mo[0][2] - Mo[0][1]);  // column m = 0 has Mo[0][0] = 0
+  B[1][0] = -Mo[0][2];
+  B[2][0] = R(0.5) * (Mo[0][2] + Mo[0][1]);
+  ax_inv(Mo[1][0], Mo[1][1], Mo[1][2], B[0][1], B[1][1], B[2][1]);
+  ax_inv(Mo[2][0], Mo[2][1], Mo[2][2], B[0][2], B[1][2], B[2][2]);
+#pragma unroll
+  for (int J = 0; J < 3; ++J) {
+    R pm, p0, pp;
+    ax_inv(B[J][0], B[J][1], B[J][2], pm, p0, pp);
+    out[DIR[J][0]] = d[DIR[J][0]] + pm;
+    out[DIR[J][1]] = d[DIR[J][1]] + p0;
+    out[DIR[J][2]] = d[DIR[J][2]] + pp;
   }
 }
 

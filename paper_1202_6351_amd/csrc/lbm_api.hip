@@ -72,7 +72,12 @@ bool validate(const lbm_params* p, char* buf) {
   if ((p->bc[0] == LBM_PERIODIC) != (p->bc[1] == LBM_PERIODIC)) { set_err(buf, "x sides: periodic on one side only"); return false; }
   if ((p->bc[2] == LBM_PERIODIC) != (p->bc[3] == LBM_PERIODIC)) { set_err(buf, "y sides: periodic on one side only"); return false; }
   const int64_t pitch = ((int64_t)p->nx + 63) / 64 * 64;
-  if ((int64_t)p->ny * pitch >= ((int64_t)1 << 31)) { set_err(buf, "lattice plane of %lld elements exceeds 2^31", (long long)(p->ny * pitch)); return false; }
+  // Kernels address a plane with 32-bit byte offsets.
+  if ((int64_t)p->ny * pitch * storage_size(p->storage) >= ((int64_t)1 << 32)) {
+    set_err(buf, "lattice plane of %lld elements x %d B exceeds 4 GiB", (long long)(p->ny * pitch),
+            storage_size(p->storage));
+    return false;
+  }
   return true;
 }
 
@@ -90,6 +95,20 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
   g.tiles_x = (int32_t)((p->nx + tx - 1) / tx);
   g.tiles_y = (int32_t)((p->ny + ty - 1) / ty);
   for (int s = 0; s < 4; ++s) g.wall[s] = p->bc[s] == LBM_WALL;
+  static const int GX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static const int GY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const int64_t esz = storage_size(p->storage);
+  const int64_t total = 9 * g.plane * esz;
+  g.fast = total < ((int64_t)1 << 32);
+  g.lattice_bytes = g.fast ? (uint32_t)total : 0u;
+  for (int k = 0; k < 9; ++k) {
+    // plane k read at (x - e_x, y - e_y): offset k*plane - e_y*pitch - e_x, >= 0
+    // for k >= 1 because plane >= 2*pitch; k = 0 has no shift.
+    const int64_t ld = (k * g.plane - (int64_t)GY[k] * pitch - GX[k]) * esz;
+    const int64_t st = k * g.plane * esz;
+    g.ld_soff[k] = g.fast ? (uint32_t)ld : 0u;
+    g.st_soff[k] = g.fast ? (uint32_t)st : 0u;
+  }
   a.w[0] = (R)p->omega3;
   a.w[1] = (R)p->omega_nu;
   a.w[2] = (R)p->omega_nu;

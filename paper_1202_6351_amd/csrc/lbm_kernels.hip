@@ -183,24 +183,99 @@ __device__ __forceinline__ Rates<R> rates(const KArgs<R>& a) {
 
 // ------------------------------------------------------------------ kernels
 
+// Buffer-resource access for the interior fast path.  One descriptor covers
+// a whole lattice; plane a is reached through a scalar offset (soffset) that
+// already includes its streaming shift, so a wavefront addresses all nine
+// loads and nine stores with one 32-bit VGPR byte offset (buffer_load/store
+// ... offen) and no per-plane address arithmetic.
+constexpr int kBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+constexpr int kNonTemporal = 2;           // cache policy: nt (no reuse expected)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferWord3);
+}
+
+template <typename S> struct BufIO;
+template <> struct BufIO<float> {
+  __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+  }
+  __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, (int)soff,
+                                          kNonTemporal);
+  }
+};
+template <> struct BufIO<double> {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  __device__ static double load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0));
+  }
+  __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, (int)soff, kNonTemporal);
+  }
+};
+template <> struct BufIO<_Float16> {
+  __device__ static _Float16 load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0));
+  }
+  __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, _Float16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, (int)soff,
+                                          kNonTemporal);
+  }
+};
+template <> struct BufIO<__bf16> {
+  __device__ static __bf16 load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0));
+  }
+  __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, __bf16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, (int)soff,
+                                          kNonTemporal);
+  }
+};
+
 // One fused stream-and-collide step: src (state n) -> dst (state n+1).
-template <typename S>
+// FM: 0 = no body force, 1 = uniform force, 2 = per-node force field.
+// A wavefront whose 64 nodes are all interior (no wrap, no wall link) pulls
+// plane a through a descriptor based at src + a*plane - e_ay*pitch - e_ax
+// with the node's own offset; wavefronts touching the domain edge take the
+// general gather with wrap and bounce-back selects.
+template <typename S, int FM>
 __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a,
                                               const S* __restrict__ src, S* __restrict__ dst) {
   using R = typename Codec<S>::R;
   const NodePos p = node_pos(a.g);
   if (!p.valid) return;
+  const Geom& g = a.g;
+  const uint32_t off = (uint32_t)(p.y * g.pitch + p.x) * (uint32_t)sizeof(S);
+  const bool inner = p.x >= 1 && p.x <= g.nx - 2 && p.y >= 1 && p.y <= g.ny - 2;
+  const bool fast = g.fast && __all(inner);
   R d[9];
-  gather<S, R>(a.g, a.wadd, src, p.x, p.y, d);
-  R Fx, Fy;
-  node_force(a, p.x, p.y, Fx, Fy);
-  R out[9];
-  NodeFwd<R> s;
-  collide(rates(a), Fx, Fy, d, out, s);
-  const int64_t c = (int64_t)p.y * a.g.pitch + p.x;
+  if (fast) {
+    const __amdgpu_buffer_rsrc_t r = rsrc(src, g.lattice_bytes);
 #pragma unroll
-  for (int k = 0; k < 9; ++k)
-    __builtin_nontemporal_store(Codec<S>::store(out[k]), dst + (int64_t)k * a.g.plane + c);
+    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(r, off, g.ld_soff[k]));
+  } else {
+    gather<S, R>(g, a.wadd, src, p.x, p.y, d);
+  }
+  R Fx = R(0), Fy = R(0);
+  if (FM == 1) {
+    Fx = a.fx;
+    Fy = a.fy;
+  } else if (FM == 2) {
+    node_force(a, p.x, p.y, Fx, Fy);
+  }
+  R out[9];
+  collide_step<R, FM != 0>(rates(a), Fx, Fy, d, out);
+  if (g.fast) {
+    const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], Codec<S>::store(out[k]));
+  } else {
+    const int64_t c = (int64_t)p.y * g.pitch + p.x;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      __builtin_nontemporal_store(Codec<S>::store(out[k]), dst + (int64_t)k * g.plane + c);
+  }
 }
 
 // Initial state f-bar = f^eq - S/2 (transformed equilibrium with hF = -F/2).
@@ -479,11 +554,18 @@ static const KArgs<typename Codec<S>::R>& args_of(const KArgsAny& a) {
   if constexpr (sizeof(typename Codec<S>::R) == 8) return a.d; else return a.f;
 }
 
+template <typename S>
+static hipError_t launch_step_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst,
+                                 hipStream_t st) {
+  const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
+  if (fm == 0) hipLaunchKernelGGL((k_step<S, 0>), grid_of(k.g), dim3(256), 0, st, k, (const S*)src, (S*)dst);
+  else if (fm == 1) hipLaunchKernelGGL((k_step<S, 1>), grid_of(k.g), dim3(256), 0, st, k, (const S*)src, (S*)dst);
+  else hipLaunchKernelGGL((k_step<S, 2>), grid_of(k.g), dim3(256), 0, st, k, (const S*)src, (S*)dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, hipStream_t st) {
-  LBM_DISPATCH(a.storage, {
-    hipLaunchKernelGGL(k_step<S>, grid_of(a.g()), dim3(256), 0, st, args_of<S>(a), (const S*)src, (S*)dst);
-    return hipGetLastError();
-  })
+  LBM_DISPATCH(a.storage, { return launch_step_fm<S>(args_of<S>(a), src, dst, st); })
 }
 
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,

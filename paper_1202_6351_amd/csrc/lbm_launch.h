@@ -15,6 +15,13 @@ struct Geom {
   int32_t tx_shift;  // log2 of the tile width TX (tiles are TX x 256/TX nodes)
   int32_t tiles_x, tiles_y;
   int32_t wall[4];   // x_lo, x_hi, y_lo, y_hi: 1 = wall, 0 = periodic
+  // Interior fast path (whole lattice below 4 GiB): byte offset of plane a
+  // from the lattice base, for the pull read (shifted by -e_a) and for the
+  // store (unshifted).
+  int32_t fast;            // 1 if the byte offsets below fit in 32 bits
+  uint32_t lattice_bytes;  // 9 * plane * sizeof(storage) (when fast)
+  uint32_t ld_soff[9];
+  uint32_t st_soff[9];
 };
 
 // Kernel arguments in the compute real R.

@@ -1,0 +1,67 @@
+// cascade_host.hip -- host build of the GPU path's per-node arithmetic
+// (paper_1202_6351_amd/csrc/cascade.h, FP64 instantiation) for CPU tests
+// against the oracle.  No kernels; exported as plain C for ctypes.
+#include "cascade.h"
+
+namespace {
+lbm::Rates<double> rates_of(const double* w, double rho0) {
+  lbm::Rates<double> r;
+  r.w3 = w[0]; r.w4 = w[1]; r.w5 = w[2]; r.w6 = w[3]; r.w7 = w[4]; r.w8 = w[5];
+  r.k3 = 1 - r.w3; r.k4 = 1 - r.w4; r.k5 = 1 - r.w5; r.k6 = 1 - r.w6; r.k7 = 1 - r.w7; r.k8 = 1 - r.w8;
+  r.rho0 = rho0;
+  return r;
+}
+}  // namespace
+
+extern "C" {
+
+// General collision (used by the adjoint's forward pass).  d, out: deviations.
+void host_collide(const double* d, double Fx, double Fy, const double* w, double rho0, double* out) {
+  lbm::NodeFwd<double> s;
+  lbm::collide(rates_of(w, rho0), Fx, Fy, d, out, s);
+}
+
+// The step kernel's specialised collision (force = 0: no body force).
+void host_collide_step(const double* d, double Fx, double Fy, const double* w, double rho0, int force,
+                       double* out) {
+  if (force) lbm::collide_step<double, true>(rates_of(w, rho0), Fx, Fy, d, out);
+  else lbm::collide_step<double, false>(rates_of(w, rho0), 0.0, 0.0, d, out);
+}
+
+// Transposed Jacobian of the collision at d: ad = J_d^T aout, aF = J_F^T aout.
+void host_collide_T(const double* d, double Fx, double Fy, const double* w, double rho0, const double* aout,
+                    double* ad, double* aF) {
+  lbm::NodeFwd<double> s;
+  double out[9];
+  const lbm::Rates<double> r = rates_of(w, rho0);
+  lbm::collide(r, Fx, Fy, d, out, s);
+  double ax = 0.0, ay = 0.0;
+  lbm::collide_T(r, s, aout, ad, ax, ay);
+  aF[0] = ax;
+  aF[1] = ay;
+}
+
+// Initial-state deviations f^eq - S/2 - w rho0 of one node.
+void host_init(double rho, double ux, double uy, double Fx, double Fy, double rho0, double* out) {
+  double Cs[3][3], Y[3][3];
+  lbm::equilibrium_cm(rho0, rho - rho0, ux, uy, -0.5 * Fx, -0.5 * Fy, Cs);
+  lbm::populations(ux, uy, Cs, Y, out);
+}
+
+// Reverse of host_init: cotangent aout -> (a_rho, a_ux, a_uy, a_Fx, a_Fy).
+void host_init_T(double rho, double ux, double uy, double Fx, double Fy, double rho0, const double* aout,
+                 double* g) {
+  double Cs[3][3], Y[3][3], v[9], aCs[3][3];
+  lbm::equilibrium_cm(rho0, rho - rho0, ux, uy, -0.5 * Fx, -0.5 * Fy, Cs);
+  lbm::populations(ux, uy, Cs, Y, v);
+  double aux = 0, auy = 0, adrho = 0, ahx = 0, ahy = 0;
+  lbm::populations_T(ux, uy, Cs, Y, aout, aCs, aux, auy);
+  lbm::equilibrium_cm_T(rho0, ux, uy, aCs, adrho, aux, auy, ahx, ahy);
+  g[0] = adrho;
+  g[1] = aux;
+  g[2] = auy;
+  g[3] = -0.5 * ahx;
+  g[4] = -0.5 * ahy;
+}
+
+}  // extern "C"
