@@ -10,8 +10,9 @@ HIP events on the library's stream.  One JSON line on stdout, also carrying:
                 nine 4-byte loads and nine 4-byte stores) over its measured
                 average duration, against MI355X's 8 TB/s;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cavity;
-  forms         FP16/BF16 deviation storage on Taylor-Green 8192 x 8192
-                (MLUPS, roofline at 36 B per node) with their velocity and
+  forms         FP16/BF16 deviation storage, round-to-nearest and
+                stochastic rounding, on Taylor-Green 8192 x 8192 (MLUPS,
+                roofline at 36 B per node) with their velocity and
                 strain-rate error against the FP64 path on Taylor-Green
                 512 x 512 after 20k steps; forward + adjoint rollout MLUPS on
                 512 x 512 FP32 (T = 2000, checkpoint every 100) with the FP32
@@ -82,10 +83,10 @@ def cavity_lattice(n, storage):
     return lat, tau
 
 
-def taylor_green_lattice(n, storage, u0=0.05, tau=0.8):
+def taylor_green_lattice(n, storage, u0=0.05, tau=0.8, rounding="nearest"):
     import workloads as W
     from paper_1202_6351_amd import Lattice, Params
-    lat = Lattice(Params(n, n, tau=tau, storage=storage), device="cuda:0")
+    lat = Lattice(Params(n, n, tau=tau, storage=storage, rounding=rounding, seed=1), device="cuda:0")
     lat.init_equilibrium(*W.taylor_green(n, u0, noise=1e-5, seed=0))
     return lat
 
@@ -120,12 +121,14 @@ def precision_errors(n=512, steps=20000):
     ref = taylor_green_lattice(n, "fp64").step(steps).macroscopic()
     ref = {k: v.cpu().numpy() for k, v in ref.items()}
     den_u = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).sum()
-    for storage in ("fp32", "fp16", "bf16"):
-        m = taylor_green_lattice(n, storage).step(steps).macroscopic()
+    for storage, rounding in (("fp32", "nearest"), ("fp16", "nearest"), ("bf16", "nearest"),
+                              ("fp16", "stochastic"), ("bf16", "stochastic")):
+        m = taylor_green_lattice(n, storage, rounding=rounding).step(steps).macroscopic()
         m = {k: v.cpu().numpy() for k, v in m.items()}
         eu = np.sqrt((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2).sum() / den_u
         es = np.abs(m["sxx"] - ref["sxx"]).sum() / np.abs(ref["sxx"]).sum()
-        out[storage] = {"u_rel_err": float(f"{eu:.3e}"), "sxx_rel_err": float(f"{es:.3e}")}
+        key = storage if rounding == "nearest" else f"{storage}_sr"
+        out[key] = {"u_rel_err": float(f"{eu:.3e}"), "sxx_rel_err": float(f"{es:.3e}")}
     torch.cuda.synchronize()
     return {"workload": f"taylor_green_{n}x{n}_u0.05_tau0.8_{steps}steps", "reference": "fp64 GPU path",
             **out}
@@ -186,6 +189,8 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
     ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64"], default=None,
                     help="time one storage mode only (profiling runs)")
+    ap.add_argument("--rounding", choices=["nearest", "stochastic"], default="nearest",
+                    help="16-bit rounding of an --only fp16/bf16 run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -201,10 +206,12 @@ def main():
 
     if args.only in ("fp16", "bf16", "fp64"):
         n = 8192 if args.only != "fp64" else 4096
-        lat = taylor_green_lattice(n, args.only) if args.only != "fp64" else cavity_lattice(n, "fp64")[0]
+        rounding = args.rounding if args.only != "fp64" else "nearest"
+        lat = (taylor_green_lattice(n, args.only, rounding=rounding) if args.only != "fp64"
+               else cavity_lattice(n, "fp64")[0])
         dt = timed_steps(lat, args.steps, args.warmup)
         mlups = n * n * args.steps / dt / 1e6
-        print(json.dumps({"only": args.only, "n": n, "mlups": round(mlups, 1),
+        print(json.dumps({"only": args.only, "rounding": rounding, "n": n, "mlups": round(mlups, 1),
                           "gbs": round(mlups * BYTES_PER_NODE[args.only] / 1e3, 1)}))
         return
 
@@ -233,15 +240,18 @@ def main():
     if args.only is None and not args.no_forms:
         forms = {}
         for storage in ("fp16", "bf16"):
-            l16 = taylor_green_lattice(8192, storage)
-            steps16 = max(10, args.steps // 4)
-            dt16 = timed_steps(l16, steps16, max(1, args.warmup // 4))
-            m16 = 8192 * 8192 * steps16 / dt16 / 1e6
-            a16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / steps16) / 1e9
-            forms[f"{storage}_dev"] = {"workload": "taylor_green_8192x8192", "mlups": round(m16, 1),
-                                       "achieved_gbs": round(a16, 1), "frac": round(a16 / HBM_PEAK_GBS, 4)}
-            del l16
-            torch.cuda.empty_cache()
+            for rounding in ("nearest", "stochastic"):
+                l16 = taylor_green_lattice(8192, storage, rounding=rounding)
+                steps16 = max(10, args.steps // 4)
+                dt16 = timed_steps(l16, steps16, max(1, args.warmup // 4))
+                m16 = 8192 * 8192 * steps16 / dt16 / 1e6
+                a16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / steps16) / 1e9
+                key = f"{storage}_dev" if rounding == "nearest" else f"{storage}_dev_sr"
+                forms[key] = {"workload": "taylor_green_8192x8192", "rounding": rounding,
+                              "mlups": round(m16, 1), "achieved_gbs": round(a16, 1),
+                              "frac": round(a16 / HBM_PEAK_GBS, 4)}
+                del l16
+                torch.cuda.empty_cache()
         forms["error_vs_fp64"] = precision_errors()
         forms["fwd_adjoint"] = adjoint_rollout()
         line["forms"] = forms

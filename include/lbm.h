@@ -71,6 +71,11 @@ typedef enum {
 } lbm_storage;
 
 typedef enum {
+  LBM_ROUND_NEAREST = 0,   /* round to nearest even                          */
+  LBM_ROUND_STOCHASTIC = 1 /* unbiased stochastic rounding (16-bit modes)    */
+} lbm_rounding;
+
+typedef enum {
   LBM_PERIODIC = 0, /* wrap-around streaming (Sec. III, Poiseuille/Taylor-Green) */
   LBM_WALL = 1      /* halfway bounce-back wall, optionally moving tangentially
                        (Sec. III, Poiseuille walls and cavity lid)            */
@@ -94,7 +99,17 @@ typedef enum {
  *               crossing two walls receives both terms).
  *   rho0        reference density (> 0): the deviation offset and the
  *               moving-wall density.
- *   storage     lbm_storage. */
+ *   storage     lbm_storage.
+ *   rounding    LBM_ROUND_NEAREST (0): stores round to nearest even.
+ *               LBM_ROUND_STOCHASTIC (1, FP16/BF16 only): each stored
+ *               deviation is rounded up or down with probability
+ *               proportional to its distance to the two neighbours
+ *               (unbiased), the random bits drawn from a counter-based hash
+ *               of (node, step, seed); deterministic for a given seed and
+ *               bit-exact across restarts.  Lets slowly evolving flows
+ *               progress whose change per step is below half an ulp of the
+ *               16-bit format.
+ *   seed        key of the stochastic-rounding hash. */
 typedef struct {
   int32_t nx, ny;
   double omega_nu;
@@ -104,6 +119,8 @@ typedef struct {
   double wall_u[4];
   double rho0;
   int32_t storage;
+  int32_t rounding;
+  uint64_t seed;
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

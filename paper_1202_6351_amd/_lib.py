@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EDEVICE", -3: "LBM_ESTAT
                 -4: "LBM_EUNSUPPORTED", -5: "LBM_EUNSTABLE"}
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 BC = {"periodic": 0, "wall": 1}
+ROUNDING = {"nearest": 0, "stochastic": 1}
 
 
 class LbmParams(ctypes.Structure):
@@ -34,6 +35,8 @@ class LbmParams(ctypes.Structure):
         ("wall_u", ctypes.c_double * 4),
         ("rho0", ctypes.c_double),
         ("storage", ctypes.c_int32),
+        ("rounding", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
     ]
 
 

@@ -69,6 +69,14 @@ bool validate(const lbm_params* p, char* buf) {
       return false;
     }
   }
+  if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC) {
+    set_err(buf, "rounding = %d unknown", p->rounding);
+    return false;
+  }
+  if (p->rounding == LBM_ROUND_STOCHASTIC && p->storage != LBM_FP16_DEV && p->storage != LBM_BF16_DEV) {
+    set_err(buf, "stochastic rounding needs FP16 or BF16 storage");
+    return false;
+  }
   if ((p->bc[0] == LBM_PERIODIC) != (p->bc[1] == LBM_PERIODIC)) { set_err(buf, "x sides: periodic on one side only"); return false; }
   if ((p->bc[2] == LBM_PERIODIC) != (p->bc[3] == LBM_PERIODIC)) { set_err(buf, "y sides: periodic on one side only"); return false; }
   const int64_t pitch = ((int64_t)p->nx + 63) / 64 * 64;
@@ -134,6 +142,15 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
 
 bool aligned(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
 
+// Key of the stochastic-rounding hash for the step from time t: mixes the
+// seed and t so every step draws fresh bits (same key scheme for every node;
+// the node index is mixed in on the device).
+uint32_t step_key(const lbm_params& p, int64_t t) {
+  if (p.rounding != LBM_ROUND_STOCHASTIC) return 0u;
+  const uint32_t a = lbm::pcg_hash((uint32_t)p.seed ^ lbm::pcg_hash((uint32_t)(p.seed >> 32)));
+  return lbm::pcg_hash(a ^ lbm::pcg_hash((uint32_t)t ^ lbm::pcg_hash((uint32_t)((uint64_t)t >> 32))));
+}
+
 lbm_status dev_err(lbm_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return LBM_OK;
   set_err(c->err, "%s: %s", what, hipGetErrorString(e));
@@ -181,6 +198,7 @@ lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* f
   c->has_force_field = force_field != nullptr;
   c->stream = (hipStream_t)stream;
   c->args.storage = p->storage;
+  c->args.stochastic = p->rounding == LBM_ROUND_STOCHASTIC;
   if (p->storage == LBM_FP64) fill_args<double>(p, c->pitch, force_field, c->args.d);
   else fill_args<float>(p, c->pitch, force_field, c->args.f);
   // Diagnostics: a fixed number of blocks (enough to fill 256 CUs), so the
@@ -249,7 +267,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (n < 0) return inval(c, "step: n < 0");
   if (!c->has_state) { set_err(c->err, "step before the state was set"); return LBM_ESTATE; }
   for (int64_t k = 0; k < n; ++k) {
-    lbm_status s = dev_err(c, lbm::launch_step(c->args, c->lat[c->cur], c->lat[c->cur ^ 1], c->stream),
+    lbm_status s = dev_err(c, lbm::launch_step(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
+                                               step_key(c->p, c->t), c->stream),
                            "step kernel");
     if (s != LBM_OK) return s;
     c->cur ^= 1;
@@ -262,7 +281,7 @@ lbm_status lbm_step_between(lbm_ctx* c, const void* src, void* dst) {
   if (!c) return LBM_EINVAL;
   if (!src || !dst || src == dst) return inval(c, "step_between: need distinct non-NULL src, dst");
   if (!aligned(src) || !aligned(dst)) return inval(c, "step_between: buffers must be 256-byte aligned");
-  return dev_err(c, lbm::launch_step(c->args, src, dst, c->stream), "step kernel");
+  return dev_err(c, lbm::launch_step(c->args, src, dst, step_key(c->p, c->t), c->stream), "step kernel");
 }
 
 lbm_status lbm_snapshot(lbm_ctx* c, void* dst) {

@@ -40,15 +40,30 @@ template <> struct Codec<float> {
   __device__ static R load(float v) { return v; }
   __device__ static float store(R v) { return v; }
 };
+// 16-bit codecs.  store() rounds to nearest even.  store_sr() rounds
+// stochastically: r supplies uniform random bits for the discarded part of
+// the FP32 significand (13 bits for binary16, 16 for bfloat16); adding them
+// to the FP32 bit pattern and truncating rounds the magnitude up with
+// probability equal to the discarded fraction (unbiased).  For binary16 the
+// truncated value is then exact in FP16 except in its subnormal range (|x| <
+// 2^-14), where the final conversion rounds to nearest.
 template <> struct Codec<_Float16> {
   using R = float;
   __device__ static R load(_Float16 v) { return (float)v; }
-  __device__ static _Float16 store(R v) { return (_Float16)v; }  // round to nearest even
+  __device__ static _Float16 store(R v) { return (_Float16)v; }
+  __device__ static _Float16 store_sr(R v, uint32_t r) {
+    const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (r & 0x1FFFu)) & 0xFFFFE000u;
+    return (_Float16)__builtin_bit_cast(float, b);
+  }
 };
 template <> struct Codec<__bf16> {
   using R = float;
   __device__ static R load(__bf16 v) { return (float)v; }
-  __device__ static __bf16 store(R v) { return (__bf16)v; }  // round to nearest even
+  __device__ static __bf16 store(R v) { return (__bf16)v; }
+  __device__ static __bf16 store_sr(R v, uint32_t r) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, v) + (r & 0xFFFFu);
+    return __builtin_bit_cast(__bf16, (uint16_t)(b >> 16));
+  }
 };
 
 // D2Q9 rest weights.
@@ -239,9 +254,9 @@ template <> struct BufIO<__bf16> {
 // plane a through a descriptor based at src + a*plane - e_ay*pitch - e_ax
 // with the node's own offset; wavefronts touching the domain edge take the
 // general gather with wrap and bounce-back selects.
-template <typename S, int FM>
-__global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a,
-                                              const S* __restrict__ src, S* __restrict__ dst) {
+template <typename S, int FM, bool SR>
+__global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                              S* __restrict__ dst, uint32_t key) {
   using R = typename Codec<S>::R;
   const NodePos p = node_pos(a.g);
   if (!p.valid) return;
@@ -266,15 +281,29 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a,
   }
   R out[9];
   collide_step<R, FM != 0>(rates(a), Fx, Fy, d, out);
+  S o[9];
+  if constexpr (SR) {
+    // 16 random bits per population: a chain of PCG hashes keyed by the node
+    // and the step's key, two 16-bit halves per hash.
+    uint32_t h = pcg_hash((uint32_t)(p.y * g.nx + p.x) ^ key);
+#pragma unroll
+    for (int k = 0; k < 9; k += 2) {
+      o[k] = Codec<S>::store_sr(out[k], h >> 16);
+      if (k + 1 < 9) o[k + 1] = Codec<S>::store_sr(out[k + 1], h);
+      h = pcg_hash(h);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o[k] = Codec<S>::store(out[k]);
+  }
   if (g.fast) {
     const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], Codec<S>::store(out[k]));
+    for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], o[k]);
   } else {
     const int64_t c = (int64_t)p.y * g.pitch + p.x;
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
-      __builtin_nontemporal_store(Codec<S>::store(out[k]), dst + (int64_t)k * g.plane + c);
+    for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
   }
 }
 
@@ -554,18 +583,29 @@ static const KArgs<typename Codec<S>::R>& args_of(const KArgsAny& a) {
   if constexpr (sizeof(typename Codec<S>::R) == 8) return a.d; else return a.f;
 }
 
-template <typename S>
-static hipError_t launch_step_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst,
+template <typename S, bool SR>
+static hipError_t launch_step_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t key,
                                  hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
-  if (fm == 0) hipLaunchKernelGGL((k_step<S, 0>), grid_of(k.g), dim3(256), 0, st, k, (const S*)src, (S*)dst);
-  else if (fm == 1) hipLaunchKernelGGL((k_step<S, 1>), grid_of(k.g), dim3(256), 0, st, k, (const S*)src, (S*)dst);
-  else hipLaunchKernelGGL((k_step<S, 2>), grid_of(k.g), dim3(256), 0, st, k, (const S*)src, (S*)dst);
+  const dim3 grid = grid_of(k.g);
+  if (fm == 0) hipLaunchKernelGGL((k_step<S, 0, SR>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, key);
+  else if (fm == 1) hipLaunchKernelGGL((k_step<S, 1, SR>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, key);
+  else hipLaunchKernelGGL((k_step<S, 2, SR>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, key);
   return hipGetLastError();
 }
 
-hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, hipStream_t st) {
-  LBM_DISPATCH(a.storage, { return launch_step_fm<S>(args_of<S>(a), src, dst, st); })
+hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t key, hipStream_t st) {
+  switch (a.storage) {
+    case 0: return launch_step_fm<double, false>(a.d, src, dst, key, st);
+    case 1: return launch_step_fm<float, false>(a.f, src, dst, key, st);
+    case 2:
+      return a.stochastic ? launch_step_fm<_Float16, true>(a.f, src, dst, key, st)
+                          : launch_step_fm<_Float16, false>(a.f, src, dst, key, st);
+    case 3:
+      return a.stochastic ? launch_step_fm<__bf16, true>(a.f, src, dst, key, st)
+                          : launch_step_fm<__bf16, false>(a.f, src, dst, key, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,

@@ -36,12 +36,23 @@ struct KArgs {
 
 struct KArgsAny {
   int32_t storage;  // lbm_storage
+  int32_t stochastic;  // 1: stochastic rounding of 16-bit stores
   KArgs<double> d;  // used when the compute real is double (FP64)
   KArgs<float> f;   // used otherwise
   const Geom& g() const { return storage == 0 ? d.g : f.g; }
 };
 
-hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, hipStream_t st);
+// PCG hash (O'Neill's permuted congruential output applied to one LCG step,
+// as tabulated by Jarzynski and Olano, "Hash Functions for GPU Rendering",
+// JCGT 2020): a counter-based generator, key -> 32 well-mixed bits.
+__host__ __device__ inline uint32_t pcg_hash(uint32_t v) {
+  const uint32_t state = v * 747796405u + 2891336453u;
+  const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
+
+// key: stochastic-rounding key of this step (ignored unless stochastic).
+hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t key, hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);

@@ -28,6 +28,8 @@ class Params:
     x-velocity for y walls); a lid is bc[3] = "wall", wall_u[3] = U.
     storage: "fp64", "fp32", "fp16" or "bf16" (the last two store the
     deviations f - w rho0 in 16 bits; arithmetic is FP32).
+    rounding: "nearest" (round to nearest even) or "stochastic" (16-bit
+    storage only: unbiased stochastic rounding keyed by `seed`).
     """
 
     nx: int
@@ -43,6 +45,8 @@ class Params:
     wall_u: Sequence[float] = (0.0, 0.0, 0.0, 0.0)
     rho0: float = 1.0
     storage: str = "fp32"
+    rounding: str = "nearest"
+    seed: int = 0
 
     def c(self) -> _lib.LbmParams:
         p = _lib.LbmParams()
@@ -57,6 +61,8 @@ class Params:
             p.wall_u[i] = float(self.wall_u[i])
         p.rho0 = float(self.rho0)
         p.storage = _lib.STORAGE[self.storage]
+        p.rounding = _lib.ROUNDING[self.rounding]
+        p.seed = int(self.seed) & ((1 << 64) - 1)
         return p
 
     @property

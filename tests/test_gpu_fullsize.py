@@ -1,0 +1,98 @@
+"""Full-size GPU parity on sampled nodes, in the launch configuration the
+benchmark times (the library picks tiles and paths by lattice size).
+
+After a few hundred steps from the benchmark's initial state, the state f(n)
+is read back, one more step is taken on the GPU, and the oracle recomputes
+that step at sampled nodes (random interior nodes, every corner, nodes on
+every wall and wrap edge) from the same f(n).  The oracle works in FP64 from
+the values the GPU actually stored, so the difference is the GPU's own
+arithmetic and storage rounding for one step:
+  FP64   <= 2e-15 absolute,
+  FP32   <= 1e-7 absolute (FP32 arithmetic on deviations of order 1e-2),
+  16-bit <= half an ulp of the stored deviation + 1e-7 (round to nearest).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+BCMAP = {"periodic": 0, "wall": 1}
+WGT = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def _sample_nodes(nx, ny, count, seed):
+    rng = np.random.default_rng(seed)
+    xs = list(rng.integers(0, nx, count))
+    ys = list(rng.integers(0, ny, count))
+    for x, y in [(0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1)]:
+        xs.append(x)
+        ys.append(y)
+    for k in range(16):  # along every edge
+        t = int(rng.integers(0, nx))
+        u = int(rng.integers(0, ny))
+        xs += [t, t, 0, nx - 1, 1, nx - 2]
+        ys += [0, ny - 1, u, u, u, u]
+    return np.array(xs, dtype=np.int32), np.array(ys, dtype=np.int32)
+
+
+def _check_one_step(lat, p_oracle, storage, warm, seed):
+    from paper_1202_6351_amd import Lattice  # noqa: F401
+    lat.step(warm)
+    f_n = lat.populations().cpu().numpy()
+    lat.step(1)
+    nx, ny = lat.params.nx, lat.params.ny
+    xs, ys = _sample_nodes(nx, ny, 3000, seed)
+    got_dev = lat.populations()
+    got = got_dev[:, torch.from_numpy(ys).long().cuda(), torch.from_numpy(xs).long().cuda()].cpu().numpy().T
+    del got_dev
+    want = oracle.step_at(p_oracle, f_n, xs, ys)
+    err = np.abs(got - want)
+    if storage == "fp64":
+        tol = 2e-15
+    elif storage == "fp32":
+        tol = 1e-7
+    else:
+        dev = np.abs(want - WGT[None, :] * p_oracle.rho0)
+        half_ulp = (2.0 ** -11 if storage == "fp16" else 2.0 ** -8) * dev
+        tol = half_ulp * (1 + 1e-3) + 1e-7
+    bad = err > tol
+    print(f"{storage} {nx}x{ny}: max one-step error {err.max():.3e} over {len(xs)} nodes")
+    assert not bad.any(), (err[bad].max(), np.argwhere(bad)[:5])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_cavity_4096_sampled(storage):
+    from paper_1202_6351_amd import Lattice, Params
+    n = 4096
+    tau = W.cavity_tau(n, 0.1, 1000.0)
+    lat = Lattice(Params(n, n, tau=tau, bc=("wall",) * 4, wall_u=(0, 0, 0, 0.1), storage=storage),
+                  device="cuda:0")
+    lat.init_equilibrium(*W.at_rest(n, n, density_noise=1e-6, seed=2))
+    p = oracle.Params(n, n, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
+    _check_one_step(lat, p, storage, 200, seed=1)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_taylor_green_8192_sampled(storage):
+    from paper_1202_6351_amd import Lattice, Params
+    n = 8192
+    lat = Lattice(Params(n, n, tau=0.8, storage=storage), device="cuda:0")
+    lat.init_equilibrium(*W.taylor_green(n, 0.05, noise=1e-5, seed=0))
+    p = oracle.Params(n, n, tau=0.8)
+    _check_one_step(lat, p, storage, 100, seed=2)
+
+
+def test_beyond_fast_path_limit_sampled():
+    """FP32 16384 x 8192 (lattice 4.8 GB > 4 GiB: every wavefront takes the
+    general gather), walls on y, periodic x, uniform force."""
+    from paper_1202_6351_amd import Lattice, Params
+    nx, ny = 16384, 8192
+    kw = dict(tau=0.7, fx=1e-6, bc=("periodic", "periodic", "wall", "wall"), wall_u=(0, 0, 0, 0.05))
+    lat = Lattice(Params(nx, ny, storage="fp32", **kw), device="cuda:0")
+    assert lat.nbytes > (1 << 32)
+    lat.init_equilibrium(*W.at_rest(nx, ny, density_noise=1e-6, seed=3))
+    p = oracle.Params(nx, ny, tau=0.7, fx=1e-6, bc=(0, 0, 1, 1), wall_u=(0, 0, 0, 0.05))
+    _check_one_step(lat, p, "fp32", 20, seed=3)

@@ -1,0 +1,107 @@
+"""16-bit deviation storage (FP16, BF16) with round-to-nearest and stochastic
+rounding: error against the FP64 path (reported; asserted only against loose
+bounds, the paper fixes no precision for this form), determinism, restart.
+
+Workload: decaying Taylor-Green vortex 256 x 256, U0 0.05, tau 0.575 (the
+same viscous decay per step as 512 x 512 at tau 0.8), 5000 steps.  Its
+velocity changes by ~3e-5 relative per step, an order of magnitude below half
+an FP16 ulp, the regime where round-to-nearest stalls and stochastic
+rounding does not.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+N, TAU, U0, STEPS = 256, 0.575, 0.05, 5000
+
+
+def _run(storage, rounding="nearest", seed=0, steps=STEPS):
+    from paper_1202_6351_amd import Lattice, Params
+    lat = Lattice(Params(N, N, tau=TAU, storage=storage, rounding=rounding, seed=seed), device="cuda:0")
+    lat.init_equilibrium(*W.taylor_green(N, U0, noise=1e-5, seed=0))
+    lat.step(steps)
+    return lat, {k: v.cpu().numpy() for k, v in lat.macroscopic().items()}
+
+
+@pytest.fixture(scope="module")
+def ref():
+    return _run("fp64")[1]
+
+
+def _uerr(m, ref):
+    num = np.sqrt((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2).sum()
+    return num / np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).sum()
+
+
+@pytest.mark.parametrize("storage,rounding,bound", [
+    ("fp32", "nearest", 1e-6),
+    ("fp16", "nearest", 0.2),
+    ("bf16", "nearest", 0.5),
+    ("fp16", "stochastic", 5e-3),
+    ("bf16", "stochastic", 3e-2),
+])
+def test_error_against_fp64(ref, storage, rounding, bound):
+    _, m = _run(storage, rounding)
+    e = _uerr(m, ref)
+    es = np.abs(m["sxx"] - ref["sxx"]).sum() / np.abs(ref["sxx"]).sum()
+    print(f"{storage} {rounding}: velocity rel err {e:.3e}, S_xx rel err {es:.3e}")
+    assert e < bound
+
+
+def test_stochastic_rounding_beats_nearest(ref):
+    """For both 16-bit formats, stochastic rounding cuts the velocity error
+    by more than 10x on this slowly decaying flow."""
+    for storage in ("fp16", "bf16"):
+        e_n = _uerr(_run(storage, "nearest")[1], ref)
+        e_s = _uerr(_run(storage, "stochastic")[1], ref)
+        assert e_s < e_n / 10, (storage, e_n, e_s)
+
+
+def test_stochastic_rounding_deterministic_and_seeded():
+    a = _run("fp16", "stochastic", seed=7, steps=50)[0].populations()
+    b = _run("fp16", "stochastic", seed=7, steps=50)[0].populations()
+    c = _run("fp16", "stochastic", seed=8, steps=50)[0].populations()
+    assert torch.equal(a, b)
+    assert not torch.equal(a, c)
+
+
+def test_stochastic_rounding_restart_bit_exact():
+    full = _run("bf16", "stochastic", seed=3, steps=60)[0].populations()
+    half, _ = _run("bf16", "stochastic", seed=3, steps=30)
+    snap = half.snapshot()
+    from paper_1202_6351_amd import Lattice, Params
+    c = Lattice(Params(N, N, tau=TAU, storage="bf16", rounding="stochastic", seed=3), device="cuda:0")
+    c.restore(snap, 30)
+    c.step(30)
+    assert torch.equal(full, c.populations())
+
+
+def test_stochastic_rounding_is_unbiased():
+    """One step of a uniform state at rest: every node computes the same FP32
+    post-collision value v (checked with an FP32 lattice started from the very
+    same stored state), and stochastic rounding stores one of the two FP16
+    neighbours of v at each node so that the field average equals v to a
+    hundredth of an ulp (262144 samples; the standard error is 1/1000 ulp)."""
+    from paper_1202_6351_amd import Lattice, Params
+    n = 512
+    delta = 3.0e-3 / 7  # rest deviation 4/9 delta = 1.9e-4: FP16 normal range
+    rho = np.full((n, n), 1.0 + delta)
+    z = np.zeros((n, n))
+    lat = Lattice(Params(n, n, tau=0.8, storage="fp16", rounding="stochastic", seed=1), device="cuda:0")
+    lat.init_equilibrium(rho, z, z)
+    f0 = lat.populations()
+    lat.step(1)
+    stored = lat.populations()[0].double().cpu().numpy()
+    ref = Lattice(Params(n, n, tau=0.8, storage="fp32"), device="cuda:0")
+    ref.set_populations(f0)
+    ref.step(1)
+    v_all = ref.populations()[0].cpu().numpy()
+    v = v_all[0, 0]
+    assert np.all(v_all == v)
+    vals = np.unique(stored)
+    assert len(vals) == 2 and vals[0] < v < vals[1], (vals, v)
+    ulp = vals[1] - vals[0]
+    assert abs(stored.mean() - v) < 0.01 * ulp
