@@ -78,6 +78,10 @@ class LbmError(RuntimeError):
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
+        # PyTorch supplies the device memory and streams: its HIP runtime must
+        # be the one in the process before liblbm.so resolves libamdhip64, or
+        # the library would start a second runtime that sees no device.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build the HIP library first "

@@ -72,7 +72,9 @@ class Rollout(torch.autograd.Function):
         mu, mu2 = lat.new_cotangent(), lat.new_cotangent()
         nseg = len(ctx.snaps)
         seg_len = [min(every, steps - s * every) for s in range(nseg)]
-        bufs = [lat.new_lattice() for _ in range(min(every, max(steps, 0)))]
+        # Segment buffers: every node of seg[i] is written by the recompute
+        # before any read (row padding is never read), so no clearing.
+        bufs = [torch.empty_like(lat.lat[0]) for _ in range(min(every, max(steps, 0)))]
         for s in range(nseg - 1, -1, -1):
             n = max(seg_len[s], 0)
             seg = [ctx.snaps[s]] + bufs[:n]
