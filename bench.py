@@ -5,10 +5,12 @@
 Headline (`value`): MLUPS of the plain FP32 step on the lid-driven cavity
 4096 x 4096 (Re 1000, lid 0.1, tau 1.7288; seeded density noise 1e-6), with
 the lattices resident in HBM: W untimed steps, then exactly K steps timed with
-HIP events on the library's stream.  One JSON line on stdout, also carrying:
-  roofline      the step kernel's algorithmic bytes (72 B per node for FP32:
-                nine 4-byte loads and nine 4-byte stores) over its measured
-                average duration, against MI355X's 8 TB/s;
+HIP events on the library's stream (lbm_step runs pairs of steps as one
+two-step launch).  One JSON line on stdout, also carrying:
+  roofline      the dominant kernel (the two-step launch) against MI355X's
+                8 TB/s: its algorithmic bytes per launch -- the state read
+                once and written once, 72 B per node for FP32, i.e. 36 B per
+                node update -- over its measured average duration;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cavity;
   forms         FP16/BF16 deviation storage, round-to-nearest and
                 stochastic rounding, on Taylor-Green 8192 x 8192 (MLUPS,
@@ -33,10 +35,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Bytes one node moves through HBM per launch: read + write of the nine
+# stored populations.  A launch advances every node by UPDATES_PER_LAUNCH steps.
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}
+UPDATES_PER_LAUNCH = 2
 METRIC = "MLUPS + % HBM peak, FP32 vs FP16-storage; fwd+adjoint MLUPS at fixed error"
 STEP_SOURCES = ["paper_1202_6351_amd/csrc/lbm_kernels.hip", "paper_1202_6351_amd/csrc/cascade.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fp32_cavity4096.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_fp32_cavity4096.txt")
 
 
 def kernel_hash() -> str:
@@ -62,7 +67,7 @@ def measured_traffic():
 
 def timed_steps(lat, steps, warmup):
     import torch
-    lat.step(warmup)
+    lat.step(warmup + (warmup & 1))  # even: the timed region starts on a two-step launch
     torch.cuda.synchronize()
     s = lat.stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -215,14 +220,16 @@ def main():
         dt = timed_steps(lat, args.steps, args.warmup)
         mlups = n * n * args.steps / dt / 1e6
         print(json.dumps({"only": args.only, "rounding": rounding, "n": n, "mlups": round(mlups, 1),
-                          "gbs": round(mlups * BYTES_PER_NODE[args.only] / 1e3, 1)}))
+                          "hbm_gbs": round(mlups / UPDATES_PER_LAUNCH * BYTES_PER_NODE[args.only] / 1e3, 1)}))
         return
 
     n = args.n
     lat, tau = cavity_lattice(n, "fp32")
     dt = timed_steps(lat, args.steps, args.warmup)
+    if args.steps % UPDATES_PER_LAUNCH:
+        raise SystemExit("--steps must be even (pairs of steps run as one launch)")
     mlups = n * n * args.steps / dt / 1e6
-    per_launch = dt / args.steps
+    per_launch = dt / (args.steps // UPDATES_PER_LAUNCH)
     achieved = BYTES_PER_NODE["fp32"] * n * n / per_launch / 1e9
     d = lat.diagnostics()  # raises on a non-finite state
     traffic = measured_traffic() if n == 4096 else None
@@ -235,7 +242,11 @@ def main():
                    "lid_u": 0.1, "storage": "fp32", "bc": "halfway bounce-back walls, moving lid"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic)},
+                     "traffic": None if traffic is None else round(traffic),
+                     "kernel": "k_step2<float> (two steps per launch)",
+                     "updates_per_launch": UPDATES_PER_LAUNCH,
+                     "bytes_per_node_update": BYTES_PER_NODE["fp32"] / UPDATES_PER_LAUNCH,
+                     "single_pass_equivalent_gbs": round(mlups * BYTES_PER_NODE["fp32"] / 1e3, 1)},
         "mass_drift_rel": float(f"{abs(d[0] / (n * n) - 1.0):.2e}"),
     }
     del lat
@@ -246,9 +257,10 @@ def main():
             for rounding in ("nearest", "stochastic"):
                 l16 = taylor_green_lattice(8192, storage, rounding=rounding)
                 steps16 = max(10, args.steps // 4)
-                dt16 = timed_steps(l16, steps16, max(1, args.warmup // 4))
+                steps16 -= steps16 % UPDATES_PER_LAUNCH
+                dt16 = timed_steps(l16, steps16, max(2, args.warmup // 4))
                 m16 = 8192 * 8192 * steps16 / dt16 / 1e6
-                a16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / steps16) / 1e9
+                a16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / (steps16 // UPDATES_PER_LAUNCH)) / 1e9
                 key = f"{storage}_dev" if rounding == "nearest" else f"{storage}_dev_sr"
                 forms[key] = {"workload": "taylor_green_8192x8192", "rounding": rounding,
                               "mlups": round(m16, 1), "achieved_gbs": round(a16, 1),

@@ -117,6 +117,9 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
     g.ld_soff[k] = g.fast ? (uint32_t)ld : 0u;
     g.st_soff[k] = g.fast ? (uint32_t)st : 0u;
   }
+  g.t2_ty = storage_size(p->storage) == 8 ? 8 : 16;
+  g.t2_tiles_x = (int32_t)((p->nx + 63) / 64);
+  g.t2_tiles_y = (int32_t)((p->ny + g.t2_ty - 1) / g.t2_ty);
   a.w[0] = (R)p->omega3;
   a.w[1] = (R)p->omega_nu;
   a.w[2] = (R)p->omega_nu;
@@ -266,7 +269,17 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return LBM_EINVAL;
   if (n < 0) return inval(c, "step: n < 0");
   if (!c->has_state) { set_err(c->err, "step before the state was set"); return LBM_ESTATE; }
-  for (int64_t k = 0; k < n; ++k) {
+  // Pairs of steps run as one two-step launch (the first step's result stays
+  // in LDS); an odd remainder runs as a single step.
+  for (int64_t k = 0; k + 1 < n; k += 2) {
+    lbm_status s = dev_err(c, lbm::launch_step2(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
+                                                step_key(c->p, c->t), step_key(c->p, c->t + 1), c->stream),
+                           "two-step kernel");
+    if (s != LBM_OK) return s;
+    c->cur ^= 1;
+    c->t += 2;
+  }
+  if (n & 1) {
     lbm_status s = dev_err(c, lbm::launch_step(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
                                                step_key(c->p, c->t), c->stream),
                            "step kernel");

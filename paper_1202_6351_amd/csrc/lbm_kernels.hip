@@ -248,6 +248,26 @@ template <> struct BufIO<__bf16> {
   }
 };
 
+// Stores of one node's nine post-collision values as the storage type, with
+// the step's rounding: nearest even, or stochastic with 16 random bits per
+// population from a chain of PCG hashes keyed by the node and the step.
+template <typename S, bool SR>
+__device__ __forceinline__ void round_out(const typename Codec<S>::R out[9], uint32_t node, uint32_t key,
+                                          S o[9]) {
+  if constexpr (SR) {
+    uint32_t h = pcg_hash(node ^ key);
+#pragma unroll
+    for (int k = 0; k < 9; k += 2) {
+      o[k] = Codec<S>::store_sr(out[k], h >> 16);
+      if (k + 1 < 9) o[k + 1] = Codec<S>::store_sr(out[k + 1], h);
+      h = pcg_hash(h);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) o[k] = Codec<S>::store(out[k]);
+  }
+}
+
 // One fused stream-and-collide step: src (state n) -> dst (state n+1).
 // FM: 0 = no body force, 1 = uniform force, 2 = per-node force field.
 // A wavefront whose 64 nodes are all interior (no wrap, no wall link) pulls
@@ -282,20 +302,7 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, con
   R out[9];
   collide_step<R, FM != 0>(rates(a), Fx, Fy, d, out);
   S o[9];
-  if constexpr (SR) {
-    // 16 random bits per population: a chain of PCG hashes keyed by the node
-    // and the step's key, two 16-bit halves per hash.
-    uint32_t h = pcg_hash((uint32_t)(p.y * g.nx + p.x) ^ key);
-#pragma unroll
-    for (int k = 0; k < 9; k += 2) {
-      o[k] = Codec<S>::store_sr(out[k], h >> 16);
-      if (k + 1 < 9) o[k + 1] = Codec<S>::store_sr(out[k + 1], h);
-      h = pcg_hash(h);
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) o[k] = Codec<S>::store(out[k]);
-  }
+  round_out<S, SR>(out, (uint32_t)(p.y * g.nx + p.x), key, o);
   if (g.fast) {
     const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
 #pragma unroll
@@ -304,6 +311,111 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, con
     const int64_t c = (int64_t)p.y * g.pitch + p.x;
 #pragma unroll
     for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
+  }
+}
+
+// Two fused steps per launch (temporal blocking).  A workgroup owns a 64 x TY
+// tile of output nodes.  Step A computes step n on the tile plus a one-node
+// ring (66 x (TY+2) nodes; periodic ring nodes at their wrapped position,
+// ring nodes beyond a wall skipped) from HBM and keeps the post-collision
+// values, rounded to the storage type exactly as a single step would store
+// them, in LDS.  Step B computes step n+1 on the tile, pulling from LDS with
+// the same bounce-back rules, and writes HBM.  HBM traffic per update is
+// halved; the ring costs (66 (TY+2)) / (64 TY) - 1 = 16 % (TY = 16) extra
+// collisions, and its loads hit L2 (neighbouring tiles run on the same XCD).
+template <typename S, int FM, bool SR, int TY>
+__global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b) {
+  using R = typename Codec<S>::R;
+  constexpr int TX = 64, EW = TX + 2, EH = TY + 2, NE = EW * EH;
+  __shared__ S mid[9][EH][EW];
+  const Geom& g = a.g;
+  const Rates<R> rt = rates(a);
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int x0 = (tile % g.t2_tiles_x) * TX, y0 = (tile / g.t2_tiles_x) * TY;
+  // Every pull of the ring is in range and no ring node touches a wall or a
+  // wrap: the buffer fast path.
+  const bool fast_a = g.fast && x0 >= 2 && x0 + TX + 1 <= g.nx - 1 && y0 >= 2 && y0 + TY + 1 <= g.ny - 1;
+  const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
+
+  // ---- step A: tile + ring, HBM -> LDS
+  for (int i = (int)threadIdx.x; i < NE; i += 256) {
+    const int ex = i % EW, ey = i / EW;
+    int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+    if (gx < 0 || gx >= g.nx) {
+      if (g.wall[gx < 0 ? 0 : 1]) continue;  // beyond a wall: never read
+      gx = ((gx % g.nx) + g.nx) % g.nx;
+    }
+    if (gy < 0 || gy >= g.ny) {
+      if (g.wall[gy < 0 ? 2 : 3]) continue;
+      gy = ((gy % g.ny) + g.ny) % g.ny;
+    }
+    R d[9];
+    if (fast_a) {
+      const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
+    } else {
+      gather<S, R>(g, a.wadd, src, gx, gy, d);
+    }
+    R Fx = R(0), Fy = R(0);
+    if (FM == 1) {
+      Fx = a.fx;
+      Fy = a.fy;
+    } else if (FM == 2) {
+      node_force(a, gx, gy, Fx, Fy);
+    }
+    R out[9];
+    collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+    S o[9];
+    round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key_a, o);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mid[k][ey][ex] = o[k];
+  }
+  __syncthreads();
+
+  // ---- step B: tile, LDS -> HBM
+  const int lx = (int)threadIdx.x & 63;
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += 4) {
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= g.nx || gy >= g.ny) continue;
+    const Edges e = edges(g, gx, gy);
+    R d[9];
+#define LBM_PULL_LDS(A)                                                                        \
+    {                                                                                          \
+      constexpr int cx = EX[A], cy = EY[A];                                                    \
+      const bool hx = (cx == 1 && e.wxl) || (cx == -1 && e.wxh);                               \
+      const bool hy = (cy == 1 && e.wyl) || (cy == -1 && e.wyh);                               \
+      R add = R(0);                                                                            \
+      if (cx != 0) add += hx ? a.wadd[(cx == 1 ? 0 : 1) * 9 + A] : R(0);                      \
+      if (cy != 0) add += hy ? a.wadd[(cy == 1 ? 2 : 3) * 9 + A] : R(0);                      \
+      d[A] = (hx || hy) ? Codec<S>::load(mid[OPP[A]][ly + 1][lx + 1]) + add                    \
+                        : Codec<S>::load(mid[A][ly + 1 - cy][lx + 1 - cx]);                    \
+    }
+    LBM_PULL_LDS(0) LBM_PULL_LDS(1) LBM_PULL_LDS(2) LBM_PULL_LDS(3) LBM_PULL_LDS(4)
+    LBM_PULL_LDS(5) LBM_PULL_LDS(6) LBM_PULL_LDS(7) LBM_PULL_LDS(8)
+#undef LBM_PULL_LDS
+    R Fx = R(0), Fy = R(0);
+    if (FM == 1) {
+      Fx = a.fx;
+      Fy = a.fy;
+    } else if (FM == 2) {
+      node_force(a, gx, gy, Fx, Fy);
+    }
+    R out[9];
+    collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+    S o[9];
+    round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key_b, o);
+    if (g.fast) {
+      const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
+      const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], o[k]);
+    } else {
+      const int64_t c = (int64_t)gy * g.pitch + gx;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
+    }
   }
 }
 
@@ -592,6 +704,37 @@ static hipError_t launch_step_fm(const KArgs<typename Codec<S>::R>& k, const voi
   else if (fm == 1) hipLaunchKernelGGL((k_step<S, 1, SR>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, key);
   else hipLaunchKernelGGL((k_step<S, 2, SR>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, key);
   return hipGetLastError();
+}
+
+template <typename S, bool SR>
+static hipError_t launch_step2_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                  uint32_t kb, hipStream_t st) {
+  const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
+  const dim3 grid((unsigned)(k.g.t2_tiles_x * k.g.t2_tiles_y));
+  constexpr int TY = sizeof(S) == 8 ? 8 : 16;
+  if (k.g.t2_ty != TY) return hipErrorInvalidValue;
+  if (fm == 0)
+    hipLaunchKernelGGL((k_step2<S, 0, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+  else if (fm == 1)
+    hipLaunchKernelGGL((k_step2<S, 1, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+  else
+    hipLaunchKernelGGL((k_step2<S, 2, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+  return hipGetLastError();
+}
+
+hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                        hipStream_t st) {
+  switch (a.storage) {
+    case 0: return launch_step2_fm<double, false>(a.d, src, dst, key_a, key_b, st);
+    case 1: return launch_step2_fm<float, false>(a.f, src, dst, key_a, key_b, st);
+    case 2:
+      return a.stochastic ? launch_step2_fm<_Float16, true>(a.f, src, dst, key_a, key_b, st)
+                          : launch_step2_fm<_Float16, false>(a.f, src, dst, key_a, key_b, st);
+    case 3:
+      return a.stochastic ? launch_step2_fm<__bf16, true>(a.f, src, dst, key_a, key_b, st)
+                          : launch_step2_fm<__bf16, false>(a.f, src, dst, key_a, key_b, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t key, hipStream_t st) {

@@ -22,6 +22,8 @@ struct Geom {
   uint32_t lattice_bytes;  // 9 * plane * sizeof(storage) (when fast)
   uint32_t ld_soff[9];
   uint32_t st_soff[9];
+  // Two-step kernel tiling: 64 x t2_ty output nodes per workgroup.
+  int32_t t2_ty, t2_tiles_x, t2_tiles_y;
 };
 
 // Kernel arguments in the compute real R.
@@ -53,6 +55,11 @@ __host__ __device__ inline uint32_t pcg_hash(uint32_t v) {
 
 // key: stochastic-rounding key of this step (ignored unless stochastic).
 hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t key, hipStream_t st);
+// Two steps in one launch: src (state n) -> dst (state n+2); key_a, key_b are
+// the stochastic-rounding keys of steps n and n+1.  Same result as two
+// launch_step calls.
+hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                        hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);

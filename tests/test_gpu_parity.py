@@ -187,3 +187,33 @@ def test_diagnostics_detect_instability():
     with pytest.raises(_lib.LbmError) as ei:
         lat.diagnostics()
     assert ei.value.status == _lib.LBM_EUNSTABLE
+
+
+# ------------------------------------------------- two-step (temporal) kernel
+
+@pytest.mark.parametrize("storage,rounding", [("fp64", "nearest"), ("fp32", "nearest"), ("fp16", "nearest"),
+                                              ("bf16", "nearest"), ("fp16", "stochastic"),
+                                              ("bf16", "stochastic")])
+@pytest.mark.parametrize("shape", [(2, 2), (3, 200), (300, 5), (67, 33), (130, 70), (200, 131)])
+@pytest.mark.parametrize("bci", [0, 1, 3])
+@pytest.mark.parametrize("force", ["none", "uniform", "field"])
+def test_two_step_launch_equals_single_steps(storage, rounding, shape, bci, force):
+    """lbm_step(n) runs pairs of steps as one two-step launch (first step kept
+    in LDS); it must give bit-for-bit the state of n single-step launches."""
+    from paper_1202_6351_amd import Lattice, Params
+    nx, ny = shape
+    bc, wu = BCS[bci]
+    frc = W.force_field(nx, ny, 1e-4, seed=3) if force == "field" else None
+    kw = dict(tau=0.7, omega3=1.1, omega6=0.9, omega7=1.2, bc=bc, wall_u=wu, storage=storage,
+              rounding=rounding, seed=5)
+    if force == "uniform":
+        kw.update(fx=2e-5, fy=-1e-5)
+    f0 = W.random_populations(nx, ny, seed=nx * 3 + ny, amp=0.05)
+    a = Lattice(Params(nx, ny, **kw), device="cuda:0", force=None if frc is None else torch.from_numpy(frc))
+    a.set_populations(f0).step(5)
+    b = Lattice(Params(nx, ny, **kw), device="cuda:0", force=None if frc is None else torch.from_numpy(frc))
+    b.set_populations(f0)
+    for _ in range(5):
+        b.step(1)  # an odd count always runs the single-step kernel
+    assert a.time == 5 and b.time == 5
+    assert torch.equal(a.populations(), b.populations())
