@@ -113,12 +113,14 @@ class Lattice:
                                          _ptr(self.force), ctypes.c_void_p(self.stream.cuda_stream),
                                          ctypes.byref(ctx)))
         self._ctx = ctx
+        self._destroy = _lib.lib().lbm_destroy  # kept: module globals may be gone at exit
 
     # ----------------------------------------------------------- plumbing
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
-        if ctx is not None and ctx.value:
-            _lib.lib().lbm_destroy(ctx)
+        destroy = getattr(self, "_destroy", None)
+        if ctx is not None and ctx.value and destroy is not None:
+            destroy(ctx)
             self._ctx = None
 
     def _check(self, status: int):
