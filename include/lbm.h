@@ -95,8 +95,9 @@ typedef enum {
  *   wall_u      tangential speed of each wall: y-velocity for x_lo/x_hi,
  *               x-velocity for y_lo/y_hi (the lid is y_hi with wall_u[3] =
  *               U).  A link crossing a moving wall receives
- *               6 rho0 w_a (e_a . U_wall) (Sec. III cavity; the corner link
- *               crossing two walls receives both terms).
+ *               6 rho0 w_a (e_a . U_wall) (Sec. III cavity).  A link
+ *               crossing two walls passes through their corner point, taken
+ *               at rest: plain bounce-back, no wall term.
  *   rho0        reference density (> 0): the deviation offset and the
  *               moving-wall density.
  *   storage     lbm_storage.

@@ -32,7 +32,10 @@
  *         dx jy + dy jx = -3 w5 f5neq; strain = those divided by rho.
  *   E6  Moving-wall term 6 rho0 w_a (e_a . U_wall), i.e. e_ax for a lid moving
  *       in x, with the reference density rho0.  A link that crosses two walls
- *       (a corner) receives the sum of the terms of the walls it crosses.
+ *       runs through the corner point where they meet; that point is taken
+ *       at rest, so such a link is plain bounce-back with no wall term.  (With
+ *       the lid term on these two links the cavity converges at first order
+ *       only; without it, at the second order Sec. III.C reports.)
  *   Initial state: f-bar = f^eq - S/2, f^eq being the D2Q9 distribution whose
  *       central moments are the Maxwellian ones (Sec. II, kappa^eq list).
  *   Walls sit half a lattice spacing outside the first/last fluid node.
@@ -313,8 +316,9 @@ static void collide_all(const lbmref_params* p, const double* f, double* post) {
  * f-bar_a(x) = f~-bar_a(x - e_a).  If x - e_a lies beyond a wall (halfway
  * bounce-back, Sec. III Poiseuille), the population that left x towards that
  * wall returns reversed: f-bar_a(x) = f~-bar_opp(a)(x), plus the moving-wall
- * term 6 rho0 w_a (e_a . U_wall) of every wall crossed (Sec. III cavity,
- * reading E6).  Periodic sides wrap. */
+ * term 6 rho0 w_a (e_a . U_wall) if exactly one wall is crossed (Sec. III
+ * cavity, reading E6: a link crossing two walls meets their corner point,
+ * which is at rest).  Periodic sides wrap. */
 static double pulled(const lbmref_params* p, const double* post, int a, int y,
                      int x) {
   int sx = x - EX[a], sy = y - EY[a];
@@ -323,14 +327,17 @@ static double pulled(const lbmref_params* p, const double* post, int a, int y,
   if (sx >= p->nx) { if (p->bc[1]) hit_xhi = 1; else sx -= p->nx; }
   if (sy < 0) { if (p->bc[2]) hit_ylo = 1; else sy += p->ny; }
   if (sy >= p->ny) { if (p->bc[3]) hit_yhi = 1; else sy -= p->ny; }
-  if (hit_xlo || hit_xhi || hit_ylo || hit_yhi) {
+  const int crossed = hit_xlo + hit_xhi + hit_ylo + hit_yhi;
+  if (crossed) {
     const double k = 6.0 * p->rho0 * WGT[a];
     double wterm = 0.0;
     /* x walls move tangentially in y; y walls move tangentially in x. */
-    if (hit_xlo) wterm += k * EY[a] * p->wall_u[0];
-    if (hit_xhi) wterm += k * EY[a] * p->wall_u[1];
-    if (hit_ylo) wterm += k * EX[a] * p->wall_u[2];
-    if (hit_yhi) wterm += k * EX[a] * p->wall_u[3];
+    if (crossed == 1) {
+      if (hit_xlo) wterm = k * EY[a] * p->wall_u[0];
+      if (hit_xhi) wterm = k * EY[a] * p->wall_u[1];
+      if (hit_ylo) wterm = k * EX[a] * p->wall_u[2];
+      if (hit_yhi) wterm = k * EX[a] * p->wall_u[3];
+    }
     return post[idx(p, OPP[a], y, x)] + wterm;
   }
   return post[idx(p, a, sy, sx)];
@@ -366,10 +373,11 @@ void lbmref_step_at(const lbmref_params* p, const double* f, int64_t count,
       int wall = 0;
       double wterm = 0.0;
       const double kw = 6.0 * p->rho0 * WGT[a];
-      if (sx < 0) { if (p->bc[0]) { wall = 1; wterm += kw * EY[a] * p->wall_u[0]; } else sx += p->nx; }
-      if (sx >= p->nx) { if (p->bc[1]) { wall = 1; wterm += kw * EY[a] * p->wall_u[1]; } else sx -= p->nx; }
-      if (sy < 0) { if (p->bc[2]) { wall = 1; wterm += kw * EX[a] * p->wall_u[2]; } else sy += p->ny; }
-      if (sy >= p->ny) { if (p->bc[3]) { wall = 1; wterm += kw * EX[a] * p->wall_u[3]; } else sy -= p->ny; }
+      if (sx < 0) { if (p->bc[0]) { ++wall; wterm = kw * EY[a] * p->wall_u[0]; } else sx += p->nx; }
+      if (sx >= p->nx) { if (p->bc[1]) { ++wall; wterm = kw * EY[a] * p->wall_u[1]; } else sx -= p->nx; }
+      if (sy < 0) { if (p->bc[2]) { ++wall; wterm = kw * EX[a] * p->wall_u[2]; } else sy += p->ny; }
+      if (sy >= p->ny) { if (p->bc[3]) { ++wall; wterm = kw * EX[a] * p->wall_u[3]; } else sy -= p->ny; }
+      if (wall > 1) wterm = 0.0; /* corner point: at rest (reading E6) */
       const int cx = wall ? x : sx, cy = wall ? y : sy;
       const int ca = wall ? OPP[a] : a;
       double fb[9], post[9], Fx, Fy;

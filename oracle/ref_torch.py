@@ -19,7 +19,9 @@ Per node (Sec. II):
     C*_22 = C_22 + w8 (rho/9 - C_22);
   f~-bar = the unique D2Q9 vector with these central moments (dense 9x9 solve).
 Streaming: pull with periodic wrap, halfway bounce-back and the moving-wall
-term 6 rho0 w_a (e_a . U_wall) (Sec. III; reading E6).
+term 6 rho0 w_a (e_a . U_wall) on links crossing one wall; a link crossing
+two walls (through their corner point, at rest) is plain bounce-back
+(Sec. III; reading E6).
 Initial state: f-bar = (distribution with central moments of the transformed
 equilibrium, Sec. II), i.e. f^eq - S/2.
 
@@ -121,9 +123,10 @@ def stream_tables(nx: int, ny: int, bc: Sequence[int], wall_u: Sequence[float],
                 k = (y * nx + x) * 9 + a
                 if hits:
                     src[k] = (y * nx + x) * 9 + OPP[a]
-                    for h in hits:
+                    if len(hits) == 1:  # two walls: their corner point, at rest
+                        h = hits[0]
                         tang = EY[a] if h < 2 else EX[a]
-                        add[k] += 6.0 * rho0 * WGT[a] * tang * wall_u[h]
+                        add[k] = 6.0 * rho0 * WGT[a] * tang * wall_u[h]
                 else:
                     src[k] = (sy * nx + sx) * 9 + a
     return torch.from_numpy(src), torch.from_numpy(add)

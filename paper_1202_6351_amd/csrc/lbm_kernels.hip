@@ -122,7 +122,9 @@ __device__ __forceinline__ Edges edges(const Geom& g, int x, int y) {
 // element offset into the lattice and the moving-wall term.  Fluid or
 // periodic link: plane A at (x - e_x, y - e_y).  Link crossing a wall
 // (halfway bounce-back): plane opp(A) at (x, y), plus 6 rho0 w_A (e_A .
-// U_wall) of each wall crossed (precomputed per side and direction in wadd).
+// U_wall) of that wall (precomputed per side and direction in wadd).  A link
+// crossing two walls passes through their corner point, which is at rest:
+// plain bounce-back, no wall term.
 template <int A, typename R>
 __device__ __forceinline__ int64_t link_src(const Geom& g, const Edges& e, int x, int y,
                                             const R* wadd, R& add) {
@@ -131,9 +133,7 @@ __device__ __forceinline__ int64_t link_src(const Geom& g, const Edges& e, int x
   const bool hy = (ey == 1 && e.wyl) || (ey == -1 && e.wyh);
   const int sx = ex == 1 ? e.xm : (ex == -1 ? e.xp : x);
   const int sy = ey == 1 ? e.ym : (ey == -1 ? e.yp : y);
-  add = R(0);
-  if (ex != 0) add += hx ? wadd[(ex == 1 ? 0 : 1) * 9 + A] : R(0);
-  if (ey != 0) add += hy ? wadd[(ey == 1 ? 2 : 3) * 9 + A] : R(0);
+  add = hx == hy ? R(0) : (hx ? wadd[(ex == 1 ? 0 : 1) * 9 + A] : wadd[(ey == 1 ? 2 : 3) * 9 + A]);
   const bool hit = hx || hy;
   const int plane = hit ? OPP[A] : A;
   const int off = hit ? y * g.pitch + x : sy * g.pitch + sx;
@@ -386,9 +386,9 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
       constexpr int cx = EX[A], cy = EY[A];                                                    \
       const bool hx = (cx == 1 && e.wxl) || (cx == -1 && e.wxh);                               \
       const bool hy = (cy == 1 && e.wyl) || (cy == -1 && e.wyh);                               \
-      R add = R(0);                                                                            \
-      if (cx != 0) add += hx ? a.wadd[(cx == 1 ? 0 : 1) * 9 + A] : R(0);                      \
-      if (cy != 0) add += hy ? a.wadd[(cy == 1 ? 2 : 3) * 9 + A] : R(0);                      \
+      const R add = hx == hy ? R(0)                                                            \
+                             : (hx ? a.wadd[(cx == 1 ? 0 : 1) * 9 + A]                         \
+                                   : a.wadd[(cy == 1 ? 2 : 3) * 9 + A]);                       \
       d[A] = (hx || hy) ? Codec<S>::load(mid[OPP[A]][ly + 1][lx + 1]) + add                    \
                         : Codec<S>::load(mid[A][ly + 1 - cy][lx + 1 - cx]);                    \
     }

@@ -135,7 +135,10 @@ def test_periodic_mass_and_momentum_budget():
 
 def test_walls_and_lid_conserve_mass():
     """Halfway bounce-back on all four sides, lid moving: total mass is
-    conserved to round-off (the lid terms of each node cancel, reading E6)."""
+    conserved to round-off.  The two lid terms of a lid node cancel; at the
+    two top corners one diagonal link crosses two walls and carries no wall
+    term (reading E6), leaving -U/6 at the left corner and +U/6 at the right
+    one, which cancel in the total."""
     n = 24
     p = oracle.Params(n, n, tau=0.6, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
     f = oracle.init_state(p, *W.at_rest(n, n, density_noise=1e-3, seed=2))
@@ -145,15 +148,21 @@ def test_walls_and_lid_conserve_mass():
 
 
 def test_lid_momentum_injection_first_step():
-    """From rest, one step of the cavity gives total x-momentum n_x U/3:
+    """From rest, one step of the cavity gives total x-momentum (n_x - 1) U/3:
     each lid node receives 6 w (e_x U) on the two diagonal links,
-    (1/36)*6*U*2 = U/3, and bounce-back of a rest equilibrium is neutral."""
+    (1/36)*6*U*2 = U/3, except the two corner nodes, whose outer diagonal link
+    crosses two walls and carries no term (reading E6): U/6 each.  Bounce-back
+    of a rest equilibrium is neutral."""
     n, U = 16, 0.1
     p = oracle.Params(n, n, tau=0.6, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, U))
     f = oracle.init_state(p, *W.at_rest(n, n))
-    d = oracle.diagnostics(p, oracle.step(p, f, 1))
-    assert abs(d[1] - n * U / 3) < 1e-15
+    f1 = oracle.step(p, f, 1)
+    d = oracle.diagnostics(p, f1)
+    assert abs(d[1] - (n - 1) * U / 3) < 1e-15
     assert abs(d[2]) < 1e-15
+    rho_top = f1[:, -1, :].sum(axis=0)  # mass moved from the left top corner to the right one
+    assert abs(rho_top[0] - (1 - U / 6)) < 1e-15 and abs(rho_top[-1] - (1 + U / 6)) < 1e-15
+    assert np.all(np.abs(rho_top[1:-1] - 1) < 1e-15)
 
 
 # ------------------------------------------------------------- symmetries
