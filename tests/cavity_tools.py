@@ -69,6 +69,7 @@ def central_difference_strain(ux, uy):
     return dudx, dvdy, shear
 
 
+
 def run_to_steady(lat, check_every=2000, tol=1e-10, max_steps=10_000_000):
     """Step until the relative change of the velocity field between checks,
     sum |u^n - u^(n-check)| / sum |u^n| (the Sec. III norm), falls below tol.
@@ -85,3 +86,125 @@ def run_to_steady(lat, check_every=2000, tol=1e-10, max_steps=10_000_000):
                 break
         prev = u
     return r
+
+
+def cavity(n, u_lid, tau, storage="fp64"):
+    """A lattice for the n x n lid-driven cavity (lid y = 1 moving in +x),
+    started from rest."""
+    import workloads as W
+    from paper_1202_6351_amd import Lattice, Params
+    lat = Lattice(Params(n, n, tau=tau, bc=("wall",) * 4, wall_u=(0, 0, 0, u_lid), storage=storage),
+                  device="cuda:0")
+    return lat.init_equilibrium(*W.at_rest(n, n))
+
+
+# ---------------------------------------------------- grid convergence (Sec. III.C)
+
+CONV_TAU, CONV_RE = 0.55, 100.0
+CONV_GRIDS = (13, 19, 25, 31, 37, 49, 61, 85, 97, 121)
+
+
+def steady_centrelines(n, tau=CONV_TAU, re=CONV_RE, tol=1e-10):
+    """Diffusive scaling: tau fixed, lid speed U = Re nu / n.  Runs the n x n
+    cavity (n odd) to a steady state and returns (positions, {(quantity,
+    line): values}) on the vertical (x = 1/2) and horizontal (y = 1/2)
+    centre lines, velocities in units of U, strain rates in units of U/L."""
+    u_lid = re * (tau - 0.5) / 3.0 / n
+    lat = cavity(n, u_lid, tau)
+    r = run_to_steady(lat, check_every=max(100, 2 * int(round(0.025 * n / u_lid))), tol=tol)
+    assert r < tol, (n, r)
+    m = {k: v.cpu().numpy() for k, v in lat.macroscopic().items()}
+    c = (n - 1) // 2
+    q = {"u": m["ux"] / u_lid, "v": m["uy"] / u_lid,
+         "dv/dy": m["syy"] * n / u_lid, "du/dy+dv/dx": 2 * m["sxy"] * n / u_lid}
+    pos = (np.arange(n) + 0.5) / n
+    return pos, {(k, line): (v[:, c] if line == "vertical" else v[c, :])
+                 for k, v in q.items() for line in ("vertical", "horizontal")}
+
+
+def convergence_slopes(grids=CONV_GRIDS, ref=401):
+    """Relative error sum |q - q_ref| / sum |q_ref| of every centre-line
+    quantity on each grid against the ref x ref solution (cubic-spline
+    interpolated onto the coarse nodes), and the least-squares slope of
+    -log(error) against log(n).  Returns ({key: slope}, {key: [errors]})."""
+    from scipy.interpolate import CubicSpline
+    rpos, rq = steady_centrelines(ref)
+    sols = [steady_centrelines(n) for n in grids]
+    slopes, errors = {}, {}
+    for key in rq:
+        errs = []
+        for pos, q in sols:
+            a = CubicSpline(rpos, rq[key])(pos)
+            errs.append(np.abs(q[key] - a).sum() / np.abs(a).sum())
+        errors[key] = errs
+        slopes[key] = -np.polyfit(np.log(np.asarray(grids, float)), np.log(errs), 1)[0]
+    return slopes, errors
+
+
+# ------------------------------------------------------------ stability (Sec. V)
+
+def stays_bounded(lat, n, u_lid, n_adv):
+    """Advance n_adv lid transit times L/U, checking after each that the
+    speed stays below 5 U (a blown-up run exceeds it or turns non-finite)."""
+    import torch
+    chunk = 2 * int(n / u_lid / 2)
+    for _ in range(int(n_adv)):
+        lat.step(chunk)
+        m = lat.macroscopic(strain=False)
+        umax = torch.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max().item()
+        if not np.isfinite(umax) or umax > 5 * u_lid:
+            return False
+    return True
+
+
+def stable_at(n, u_lid, cell_re, n_adv=100):
+    """Impulsively started cavity at cell Reynolds number U/nu: bounded for
+    n_adv transit times?"""
+    return stays_bounded(cavity(n, u_lid, 3.0 * u_lid / cell_re + 0.5), n, u_lid, n_adv)
+
+
+def max_stable_cell_re(n, u_lid=0.1, lo=10.0, hi=2000.0, rel=0.01, n_adv=100):
+    """Largest cell Reynolds number at which the impulsively started cavity
+    stays bounded (geometric bisection to a relative width rel)."""
+    while hi / lo > 1 + rel:
+        mid = (lo * hi) ** 0.5
+        lo, hi = (mid, hi) if stable_at(n, u_lid, mid, n_adv) else (lo, mid)
+    return lo
+
+
+def max_stable_cell_re_continuation(n, u_lid=0.1, start=40.0, factor=1.02, n_adv=20):
+    """Lid speed fixed, tau lowered stage by stage: each stage restarts from
+    the previous stage's state with the cell Reynolds number raised by
+    `factor` and runs n_adv transit times.  Returns the last bounded stage."""
+    from paper_1202_6351_amd import Lattice, Params
+    lat = cavity(n, u_lid, 3.0 * u_lid / start + 0.5)
+    assert stays_bounded(lat, n, u_lid, 50)
+    rec = start
+    while rec < 5000:
+        nxt = Lattice(Params(n, n, tau=3.0 * u_lid / (rec * factor) + 0.5, bc=("wall",) * 4,
+                             wall_u=(0, 0, 0, u_lid), storage="fp64"), device="cuda:0")
+        nxt.restore(lat.snapshot(), lat.time)
+        if not stays_bounded(nxt, n, u_lid, n_adv):
+            break
+        lat, rec = nxt, rec * factor
+    return rec
+
+
+if __name__ == "__main__":
+    # Prints the cavity convergence and stability figures of the GPU path:
+    #   python -m tests.cavity_tools convergence [ref_grid]
+    #   python -m tests.cavity_tools stability
+    import json
+    import sys
+    what = sys.argv[1] if len(sys.argv) > 1 else "convergence"
+    if what == "convergence":
+        ref = int(sys.argv[2]) if len(sys.argv) > 2 else 401
+        sl, er = convergence_slopes(ref=ref)
+        for k, v in sl.items():
+            print(json.dumps({"quantity": k[0], "line": k[1], "slope": round(v, 3), "ref": ref,
+                              "errors": [float(f"{e:.3e}") for e in er[k]]}), flush=True)
+    elif what == "stability":
+        for n in (101, 201, 401):
+            print(json.dumps({"n": n, "u_lid": 0.1,
+                              "impulsive": round(max_stable_cell_re(n), 2),
+                              "continuation": round(max_stable_cell_re_continuation(n), 2)}), flush=True)

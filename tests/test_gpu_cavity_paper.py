@@ -56,10 +56,7 @@ _CACHE = {}
 
 def _steady(re_):
     if re_ not in _CACHE:
-        from paper_1202_6351_amd import Lattice, Params
-        lat = Lattice(Params(N, N, tau=W.cavity_tau(N, U, re_), bc=("wall",) * 4, wall_u=(0, 0, 0, U),
-                             storage="fp64"), device="cuda:0")
-        lat.init_equilibrium(*W.at_rest(N, N))
+        lat = C.cavity(N, U, W.cavity_tau(N, U, re_))
         r = C.run_to_steady(lat)
         assert r < 1e-10, f"Re {re_}: not steady after {lat.time} steps (residual {r:.2e})"
         m = {k: v.cpu().numpy() for k, v in lat.macroscopic().items()}
