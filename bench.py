@@ -5,16 +5,22 @@
 Headline (`value`): MLUPS of the plain FP32 step on the lid-driven cavity
 4096 x 4096 (Re 1000, lid 0.1, tau 1.7288; seeded density noise 1e-6), with
 the lattices resident in HBM: W untimed steps, then exactly K steps timed with
-HIP events on the library's stream (lbm_step runs pairs of steps as one
-two-step launch).  One JSON line on stdout, also carrying:
-  roofline      the dominant kernel (the two-step launch) against MI355X's
-                8 TB/s: its algorithmic bytes per launch -- the state read
-                once and written once, 72 B per node for FP32, i.e. 36 B per
-                node update -- over its measured average duration;
+HIP events on the library's stream (lbm_step fuses three steps per launch in
+FP32 and FP64, two in FP16/BF16).  One JSON line on stdout, also carrying:
+  roofline      the dominant kernel (the three-step FP32 launch) against
+                MI355X's 8 TB/s: its algorithmic bytes per launch -- the
+                method's 72 B per FP32 cell update (nine populations read and
+                nine written) times the three updates of every node -- over
+                its measured average duration (an event between the whole
+                groups and any remainder of K separates the dominant
+                launches).  Fusing three steps moves only a third of those
+                bytes (the state read and written once per launch, 24 B per
+                update), so frac can exceed 1; the bytes actually moved and
+                their rate are reported beside it;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cavity;
   forms         FP16/BF16 deviation storage, round-to-nearest and
                 stochastic rounding, on Taylor-Green 8192 x 8192 (MLUPS,
-                roofline at 36 B per node) with their velocity and
+                roofline at 36 B per node and launch) with their velocity and
                 strain-rate error against the FP64 path on Taylor-Green
                 512 x 512 after 20k steps; forward + adjoint rollout MLUPS on
                 512 x 512 FP32 (T = 2000, checkpoint every 100) with the FP32
@@ -35,13 +41,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-# Bytes one node moves through HBM per launch: read + write of the nine
-# stored populations.  A launch advances every node by UPDATES_PER_LAUNCH steps.
+# Algorithmic bytes per cell update (nine populations read, nine written),
+# which is also what one node moves through HBM per launch: a launch reads
+# and writes the state once and advances every node by UPDATES_PER_LAUNCH
+# steps (the library's grouping per storage mode).
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}
-UPDATES_PER_LAUNCH = 2
+UPDATES_PER_LAUNCH = {"fp64": 3, "fp32": 3, "fp16": 2, "bf16": 2}
 METRIC = "MLUPS + % HBM peak, FP32 vs FP16-storage; fwd+adjoint MLUPS at fixed error"
 STEP_SOURCES = ["paper_1202_6351_amd/csrc/lbm_kernels.hip", "paper_1202_6351_amd/csrc/cascade.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_fp32_cavity4096.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step3_fp32_cavity4096.txt")
 
 
 def kernel_hash() -> str:
@@ -65,17 +73,24 @@ def measured_traffic():
     return float(m_val.group(1))
 
 
-def timed_steps(lat, steps, warmup):
+def timed_steps(lat, steps, warmup, group):
+    """Time exactly `steps` steps with HIP events on the library's stream.
+    Returns (seconds for all steps, seconds for the whole groups, number of
+    group launches): the remainder of steps modulo the group runs after an
+    intermediate event, so the second figure covers one kernel only."""
     import torch
-    lat.step(warmup + (warmup & 1))  # even: the timed region starts on a two-step launch
+    lat.step(warmup)
     torch.cuda.synchronize()
     s = lat.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    whole = steps - steps % group
     e0.record(s)
-    lat.step(steps)
+    lat.step(whole)
     e1.record(s)
+    lat.step(steps - whole)
+    e2.record(s)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3  # seconds
+    return e0.elapsed_time(e2) / 1e3, e0.elapsed_time(e1) / 1e3, whole // group
 
 
 def cavity_lattice(n, storage):
@@ -192,7 +207,7 @@ def copy_calibration(nbytes=1 << 30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=2100)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
     ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64"], default=None,
@@ -217,20 +232,25 @@ def main():
         rounding = args.rounding if args.only != "fp64" else "nearest"
         lat = (taylor_green_lattice(n, args.only, rounding=rounding) if args.only != "fp64"
                else cavity_lattice(n, "fp64")[0])
-        dt = timed_steps(lat, args.steps, args.warmup)
+        grp = UPDATES_PER_LAUNCH[args.only]
+        dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
         mlups = n * n * args.steps / dt / 1e6
+        gbs = BYTES_PER_NODE[args.only] * n * n * launches / dt_main / 1e9 if launches else None
         print(json.dumps({"only": args.only, "rounding": rounding, "n": n, "mlups": round(mlups, 1),
-                          "hbm_gbs": round(mlups / UPDATES_PER_LAUNCH * BYTES_PER_NODE[args.only] / 1e3, 1)}))
+                          "updates_per_launch": grp, "moved_gbs": None if gbs is None else round(gbs, 1),
+                          "launch_us": round(dt_main / launches * 1e6, 2) if launches else None}))
         return
 
     n = args.n
     lat, tau = cavity_lattice(n, "fp32")
-    dt = timed_steps(lat, args.steps, args.warmup)
-    if args.steps % UPDATES_PER_LAUNCH:
-        raise SystemExit("--steps must be even (pairs of steps run as one launch)")
+    grp = UPDATES_PER_LAUNCH["fp32"]
+    if args.steps < grp:
+        raise SystemExit(f"--steps must be at least {grp} (one fused launch)")
+    dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
     mlups = n * n * args.steps / dt / 1e6
-    per_launch = dt / (args.steps // UPDATES_PER_LAUNCH)
-    achieved = BYTES_PER_NODE["fp32"] * n * n / per_launch / 1e9
+    per_launch = dt_main / launches
+    moved = BYTES_PER_NODE["fp32"] * n * n / per_launch / 1e9  # HBM bytes the launch moves
+    achieved = moved * grp  # algorithmic: 72 B per cell update, grp updates per node
     d = lat.diagnostics()  # raises on a non-finite state
     traffic = measured_traffic() if n == 4096 else None
     line = {
@@ -243,10 +263,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": "k_step2<float> (two steps per launch)",
-                     "updates_per_launch": UPDATES_PER_LAUNCH,
-                     "bytes_per_node_update": BYTES_PER_NODE["fp32"] / UPDATES_PER_LAUNCH,
-                     "single_pass_equivalent_gbs": round(mlups * BYTES_PER_NODE["fp32"] / 1e3, 1)},
+                     "kernel": "k_step3<float> (three steps per launch)",
+                     "launch_us": round(per_launch * 1e6, 2),
+                     "updates_per_launch": grp,
+                     "alg_bytes_per_update": BYTES_PER_NODE["fp32"],
+                     "moved_bytes_per_update": BYTES_PER_NODE["fp32"] / grp,
+                     "moved_gbs": round(moved, 1), "moved_frac": round(moved / HBM_PEAK_GBS, 4),
+                     "note": "three steps per launch: the state crosses HBM once per three updates, "
+                             "so the algorithmic rate exceeds the single-pass HBM roofline"},
         "mass_drift_rel": float(f"{abs(d[0] / (n * n) - 1.0):.2e}"),
     }
     del lat
@@ -256,11 +280,12 @@ def main():
         for storage in ("fp16", "bf16"):
             for rounding in ("nearest", "stochastic"):
                 l16 = taylor_green_lattice(8192, storage, rounding=rounding)
+                g16 = UPDATES_PER_LAUNCH[storage]
                 steps16 = max(10, args.steps // 4)
-                steps16 -= steps16 % UPDATES_PER_LAUNCH
-                dt16 = timed_steps(l16, steps16, max(2, args.warmup // 4))
+                steps16 -= steps16 % g16
+                dt16, _, launches16 = timed_steps(l16, steps16, max(2, args.warmup // 4), g16)
                 m16 = 8192 * 8192 * steps16 / dt16 / 1e6
-                a16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / (steps16 // UPDATES_PER_LAUNCH)) / 1e9
+                a16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / launches16) / 1e9
                 key = f"{storage}_dev" if rounding == "nearest" else f"{storage}_dev_sr"
                 forms[key] = {"workload": "taylor_green_8192x8192", "rounding": rounding,
                               "mlups": round(m16, 1), "achieved_gbs": round(a16, 1),

@@ -120,6 +120,9 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
   g.t2_ty = storage_size(p->storage) == 8 ? 8 : 16;
   g.t2_tiles_x = (int32_t)((p->nx + 63) / 64);
   g.t2_tiles_y = (int32_t)((p->ny + g.t2_ty - 1) / g.t2_ty);
+  g.t3_ty = storage_size(p->storage) == 8 ? 4 : 12;
+  g.t3_tiles_x = g.t2_tiles_x;
+  g.t3_tiles_y = (int32_t)((p->ny + g.t3_ty - 1) / g.t3_ty);
   a.w[0] = (R)p->omega3;
   a.w[1] = (R)p->omega_nu;
   a.w[2] = (R)p->omega_nu;
@@ -142,6 +145,11 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
       a.wadd[s * 9 + k] = (R)(6.0 * p->rho0 * W[k] * tang * p->wall_u[s]);
     }
 }
+
+// Steps fused per launch: three for FP32 and FP64, whose two-step launch
+// leaves VALU idle while HBM streams; two for the 16-bit modes, whose
+// two-step launch already keeps VALU busy.
+int steps_per_launch(int32_t storage) { return (storage == LBM_FP32 || storage == LBM_FP64) ? 3 : 2; }
 
 bool aligned(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
 
@@ -269,9 +277,21 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return LBM_EINVAL;
   if (n < 0) return inval(c, "step: n < 0");
   if (!c->has_state) { set_err(c->err, "step before the state was set"); return LBM_ESTATE; }
-  // Pairs of steps run as one two-step launch (the first step's result stays
-  // in LDS); an odd remainder runs as a single step.
-  for (int64_t k = 0; k + 1 < n; k += 2) {
+  // Steps run in groups of steps_per_launch(storage) fused in one launch
+  // (intermediate states stay in LDS); the remainder runs as a two-step
+  // and/or a single-step launch.
+  const int group = steps_per_launch(c->p.storage);
+  int64_t left = n;
+  for (; group == 3 && left >= 3; left -= 3) {
+    lbm_status s = dev_err(c, lbm::launch_step3(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
+                                                step_key(c->p, c->t), step_key(c->p, c->t + 1),
+                                                step_key(c->p, c->t + 2), c->stream),
+                           "three-step kernel");
+    if (s != LBM_OK) return s;
+    c->cur ^= 1;
+    c->t += 3;
+  }
+  for (; left >= 2; left -= 2) {
     lbm_status s = dev_err(c, lbm::launch_step2(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
                                                 step_key(c->p, c->t), step_key(c->p, c->t + 1), c->stream),
                            "two-step kernel");
@@ -279,7 +299,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     c->cur ^= 1;
     c->t += 2;
   }
-  if (n & 1) {
+  if (left == 1) {
     lbm_status s = dev_err(c, lbm::launch_step(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
                                                step_key(c->p, c->t), c->stream),
                            "step kernel");

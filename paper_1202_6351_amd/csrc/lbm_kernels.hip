@@ -314,98 +314,214 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, con
   }
 }
 
-// Two fused steps per launch (temporal blocking).  A workgroup owns a 64 x TY
-// tile of output nodes.  Step A computes step n on the tile plus a one-node
-// ring (66 x (TY+2) nodes; periodic ring nodes at their wrapped position,
-// ring nodes beyond a wall skipped) from HBM and keeps the post-collision
-// values, rounded to the storage type exactly as a single step would store
-// them, in LDS.  Step B computes step n+1 on the tile, pulling from LDS with
-// the same bounce-back rules, and writes HBM.  HBM traffic per update is
-// halved; the ring costs (66 (TY+2)) / (64 TY) - 1 = 16 % (TY = 16) extra
-// collisions, and its loads hit L2 (neighbouring tiles run on the same XCD).
-template <typename S, int FM, bool SR, int TY>
-__global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
-                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b) {
-  using R = typename Codec<S>::R;
-  constexpr int TX = 64, EW = TX + 2, EH = TY + 2, NE = EW * EH;
-  __shared__ S mid[9][EH][EW];
-  const Geom& g = a.g;
-  const Rates<R> rt = rates(a);
-  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  const int x0 = (tile % g.t2_tiles_x) * TX, y0 = (tile / g.t2_tiles_x) * TY;
-  // Every pull of the ring is in range and no ring node touches a wall or a
-  // wrap: the buffer fast path.
-  const bool fast_a = g.fast && x0 >= 2 && x0 + TX + 1 <= g.nx - 1 && y0 >= 2 && y0 + TY + 1 <= g.ny - 1;
-  const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
+// ---- multi-step launches (temporal blocking) ----------------------------
+//
+// A workgroup owns a 64 x TY tile of output nodes and keeps a window of the
+// tile plus an H-node ring in LDS.  Every intermediate value is rounded to the
+// storage type exactly as a stored step would round it (stochastic keys
+// included), so a K-step launch is bit-for-bit K single steps.  Window cells
+// hold nodes at their wrapped position on periodic sides; cells beyond a wall
+// are never computed or read (links across a wall bounce back from the
+// node's own cell).
 
-  // ---- step A: tile + ring, HBM -> LDS
-  for (int i = (int)threadIdx.x; i < NE; i += 256) {
-    const int ex = i % EW, ey = i / EW;
-    int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
-    if (gx < 0 || gx >= g.nx) {
-      if (g.wall[gx < 0 ? 0 : 1]) continue;  // beyond a wall: never read
-      gx = ((gx % g.nx) + g.nx) % g.nx;
-    }
-    if (gy < 0 || gy >= g.ny) {
-      if (g.wall[gy < 0 ? 2 : 3]) continue;
-      gy = ((gy % g.ny) + g.ny) % g.ny;
-    }
-    R d[9];
-    if (fast_a) {
-      const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
+// Global node of window cell (wx, wy) in unwrapped coordinates: false if it
+// lies beyond a wall, else its wrapped position.
+__device__ __forceinline__ bool window_node(const Geom& g, int wx, int wy, int& gx, int& gy) {
+  if (wx < 0 || wx >= g.nx) {
+    if (g.wall[wx < 0 ? 0 : 1]) return false;
+    wx = ((wx % g.nx) + g.nx) % g.nx;
+  }
+  if (wy < 0 || wy >= g.ny) {
+    if (g.wall[wy < 0 ? 2 : 3]) return false;
+    wy = ((wy % g.ny) + g.ny) % g.ny;
+  }
+  gx = wx;
+  gy = wy;
+  return true;
+}
+
+// The nine populations streaming into node (gx, gy), held in window cell
+// (cx, cy) whose neighbours hold the previous step's post-collision values.
+// WALLS = false: the caller knows that no link of the node crosses a wall.
+template <bool WALLS, typename S, typename R, int EH, int EW>
+__device__ __forceinline__ void pull_window(const KArgs<R>& a, int gx, int gy, const S (&mid)[9][EH][EW],
+                                            int cx, int cy, R d[9]) {
+  if constexpr (!WALLS) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
-    } else {
-      gather<S, R>(g, a.wadd, src, gx, gy, d);
-    }
-    R Fx = R(0), Fy = R(0);
-    if (FM == 1) {
-      Fx = a.fx;
-      Fy = a.fy;
-    } else if (FM == 2) {
-      node_force(a, gx, gy, Fx, Fy);
-    }
+    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(mid[k][cy - EY[k]][cx - EX[k]]);
+    return;
+  }
+  const Edges e = edges(a.g, gx, gy);
+#define LBM_PULL_WIN(A)                                                                        \
+  {                                                                                            \
+    constexpr int ax = EX[A], ay = EY[A];                                                      \
+    const bool hx = (ax == 1 && e.wxl) || (ax == -1 && e.wxh);                                 \
+    const bool hy = (ay == 1 && e.wyl) || (ay == -1 && e.wyh);                                 \
+    const R add = hx == hy ? R(0)                                                              \
+                           : (hx ? a.wadd[(ax == 1 ? 0 : 1) * 9 + A]                           \
+                                 : a.wadd[(ay == 1 ? 2 : 3) * 9 + A]);                         \
+    d[A] = (hx || hy) ? Codec<S>::load(mid[OPP[A]][cy][cx]) + add                              \
+                      : Codec<S>::load(mid[A][cy - ay][cx - ax]);                              \
+  }
+  LBM_PULL_WIN(0) LBM_PULL_WIN(1) LBM_PULL_WIN(2) LBM_PULL_WIN(3) LBM_PULL_WIN(4)
+  LBM_PULL_WIN(5) LBM_PULL_WIN(6) LBM_PULL_WIN(7) LBM_PULL_WIN(8)
+#undef LBM_PULL_WIN
+}
+
+template <int FM, typename R>
+__device__ __forceinline__ void force_at(const KArgs<R>& a, int gx, int gy, R& Fx, R& Fy) {
+  Fx = R(0);
+  Fy = R(0);
+  if (FM == 1) {
+    Fx = a.fx;
+    Fy = a.fy;
+  } else if (FM == 2) {
+    node_force(a, gx, gy, Fx, Fy);
+  }
+}
+
+// Step n for one window cell from its nine pulled populations d, rounded and
+// kept in LDS.
+template <typename S, int FM, bool SR, int EH, int EW>
+__device__ __forceinline__ void collide_into_window(const KArgs<typename Codec<S>::R>& a,
+                                                    const Rates<typename Codec<S>::R>& rt, int gx, int gy,
+                                                    const typename Codec<S>::R d[9], uint32_t key,
+                                                    S (&mid)[9][EH][EW], int cx, int cy) {
+  using R = typename Codec<S>::R;
+  R Fx, Fy;
+  force_at<FM>(a, gx, gy, Fx, Fy);
+  R out[9];
+  collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+  S o[9];
+  round_out<S, SR>(out, (uint32_t)(gy * a.g.nx + gx), key, o);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[k];
+}
+
+// Pull of window cell (gx, gy) for the first stage: from HBM, through the
+// buffer fast path when the whole window allows it.
+template <typename S>
+__device__ __forceinline__ void pull_hbm(const KArgs<typename Codec<S>::R>& a, __amdgpu_buffer_rsrc_t rs,
+                                         const S* __restrict__ src, bool fast, int gx, int gy,
+                                         typename Codec<S>::R d[9]) {
+  using R = typename Codec<S>::R;
+  const Geom& g = a.g;
+  if (fast) {
+    const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
+  } else {
+    gather<S, R>(g, a.wadd, src, gx, gy, d);
+  }
+}
+
+// First stage: step n on every cell of the window (origin (wx0, wy0) in
+// unwrapped coordinates) from HBM into LDS, one cell at a time.  fast: no
+// cell of the window pulls across a wall or a wrap, and the lattice is below
+// 4 GiB.
+template <typename S, int FM, bool SR, int EH, int EW>
+__device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>& a,
+                                               const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
+                                               int wx0, int wy0, bool fast, uint32_t key, S (&mid)[9][EH][EW]) {
+  using R = typename Codec<S>::R;
+  const __amdgpu_buffer_rsrc_t rs = rsrc(src, a.g.lattice_bytes);
+  for (int i = (int)threadIdx.x; i < EW * EH; i += 256) {
+    const int cx = i % EW, cy = i / EW;
+    int gx, gy;
+    if (!window_node(a.g, wx0 + cx, wy0 + cy, gx, gy)) continue;
+    R d[9];
+    pull_hbm<S>(a, rs, src, fast, gx, gy, d);
+    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx, gy, d, key, mid, cx, cy);
+  }
+}
+
+// The same with every load of the thread's cells issued before the first
+// collision, so that HBM latency is paid once per stage rather than once per
+// cell.
+template <typename S, int FM, bool SR, int EH, int EW>
+__device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Codec<S>::R>& a,
+                                                        const Rates<typename Codec<S>::R>& rt,
+                                                        const S* __restrict__ src, int wx0, int wy0, bool fast,
+                                                        uint32_t key, S (&mid)[9][EH][EW]) {
+  using R = typename Codec<S>::R;
+  constexpr int NPT = (EW * EH + 255) / 256;
+  const __amdgpu_buffer_rsrc_t rs = rsrc(src, a.g.lattice_bytes);
+  R d[NPT][9];
+  int gx[NPT], gy[NPT];
+  bool live[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = (int)threadIdx.x + 256 * j;
+    live[j] = i < EW * EH && window_node(a.g, wx0 + i % EW, wy0 + i / EW, gx[j], gy[j]);
+    if (live[j]) pull_hbm<S>(a, rs, src, fast, gx[j], gy[j], d[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = (int)threadIdx.x + 256 * j;
+    if (live[j]) collide_into_window<S, FM, SR, EH, EW>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW);
+  }
+}
+
+// Middle stage, in place: one step on the window cells at most RING nodes
+// outside the tile (the window has an H-node ring).  Every thread pulls and
+// collides its cells into registers; after a barrier it writes them back.
+// WALLS = false: the window lies inside the domain and no cell's link
+// crosses a wall.
+template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING>
+__device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& a,
+                                             const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
+                                             uint32_t key, S (&mid)[9][EH][EW]) {
+  using R = typename Codec<S>::R;
+  constexpr int RW = EW - 2 * (H - RING), RH = EH - 2 * (H - RING), NPT = (RW * RH + 255) / 256;
+  const Geom& g = a.g;
+  S o[NPT][9];
+  bool live[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = (int)threadIdx.x + 256 * j;
+    const int cx = H - RING + i % RW, cy = H - RING + i / RW;
+    int gx = wx0 + cx, gy = wy0 + cy;
+    live[j] = i < RW * RH && (!WALLS || window_node(g, wx0 + cx, wy0 + cy, gx, gy));
+    if (!live[j]) continue;
+    R d[9];
+    pull_window<WALLS, S, R, EH, EW>(a, gx, gy, mid, cx, cy, d);
+    R Fx, Fy;
+    force_at<FM>(a, gx, gy, Fx, Fy);
     R out[9];
     collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
-    S o[9];
-    round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key_a, o);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) mid[k][ey][ex] = o[k];
+    round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key, o[j]);
   }
   __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    if (!live[j]) continue;
+    const int i = (int)threadIdx.x + 256 * j;
+    const int cx = H - RING + i % RW, cy = H - RING + i / RW;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[j][k];
+  }
+  __syncthreads();
+}
 
-  // ---- step B: tile, LDS -> HBM
+// Last stage: one step on the 64 x TY tile from LDS to HBM.
+template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H>
+__device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& a,
+                                             const Rates<typename Codec<S>::R>& rt, int x0, int y0,
+                                             uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst) {
+  using R = typename Codec<S>::R;
+  const Geom& g = a.g;
   const int lx = (int)threadIdx.x & 63;
   for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += 4) {
     const int gx = x0 + lx, gy = y0 + ly;
     if (gx >= g.nx || gy >= g.ny) continue;
-    const Edges e = edges(g, gx, gy);
     R d[9];
-#define LBM_PULL_LDS(A)                                                                        \
-    {                                                                                          \
-      constexpr int cx = EX[A], cy = EY[A];                                                    \
-      const bool hx = (cx == 1 && e.wxl) || (cx == -1 && e.wxh);                               \
-      const bool hy = (cy == 1 && e.wyl) || (cy == -1 && e.wyh);                               \
-      const R add = hx == hy ? R(0)                                                            \
-                             : (hx ? a.wadd[(cx == 1 ? 0 : 1) * 9 + A]                         \
-                                   : a.wadd[(cy == 1 ? 2 : 3) * 9 + A]);                       \
-      d[A] = (hx || hy) ? Codec<S>::load(mid[OPP[A]][ly + 1][lx + 1]) + add                    \
-                        : Codec<S>::load(mid[A][ly + 1 - cy][lx + 1 - cx]);                    \
-    }
-    LBM_PULL_LDS(0) LBM_PULL_LDS(1) LBM_PULL_LDS(2) LBM_PULL_LDS(3) LBM_PULL_LDS(4)
-    LBM_PULL_LDS(5) LBM_PULL_LDS(6) LBM_PULL_LDS(7) LBM_PULL_LDS(8)
-#undef LBM_PULL_LDS
-    R Fx = R(0), Fy = R(0);
-    if (FM == 1) {
-      Fx = a.fx;
-      Fy = a.fy;
-    } else if (FM == 2) {
-      node_force(a, gx, gy, Fx, Fy);
-    }
+    pull_window<WALLS, S, R, EH, EW>(a, gx, gy, mid, lx + H, ly + H, d);
+    R Fx, Fy;
+    force_at<FM>(a, gx, gy, Fx, Fy);
     R out[9];
     collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
     S o[9];
-    round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key_b, o);
+    round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key, o);
     if (g.fast) {
       const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
       const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
@@ -416,6 +532,69 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
 #pragma unroll
       for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
     }
+  }
+}
+
+// Tile origin of this workgroup; interior: every pull of the window with an
+// H-node ring stays inside the domain (no wall link, no wrap); fast: interior
+// and the lattice takes the buffer path.
+template <int TY, int H>
+__device__ __forceinline__ void tile_origin(const Geom& g, int tiles_x, int& x0, int& y0, bool& interior,
+                                            bool& fast) {
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  x0 = (tile % tiles_x) * 64;
+  y0 = (tile / tiles_x) * TY;
+  interior = x0 - H - 1 >= 0 && x0 + 64 + H <= g.nx - 1 && y0 - H - 1 >= 0 && y0 + TY + H <= g.ny - 1;
+  fast = g.fast && interior;
+}
+
+// Two fused steps per launch.  Step n on the tile plus a one-node ring
+// (66 x (TY+2) nodes) from HBM into LDS, then step n+1 on the tile from LDS
+// to HBM.  HBM traffic per update is halved; the ring costs
+// (66 (TY+2)) / (64 TY) - 1 = 16 % (TY = 16) extra collisions, and its loads
+// hit L2 (neighbouring tiles run on the same XCD).
+template <typename S, int FM, bool SR, int TY>
+__global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b) {
+  constexpr int H = 1, EW = 64 + 2 * H, EH = TY + 2 * H;
+  __shared__ S mid[9][EH][EW];
+  const auto rt = rates(a);
+  int x0, y0;
+  bool interior, fast;
+  tile_origin<TY, H>(a.g, a.g.t2_tiles_x, x0, y0, interior, fast);
+  stage_from_hbm<S, FM, SR, EH, EW>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  __syncthreads();
+  if (interior)  // workgroup-uniform
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_b, mid, dst);
+  else
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_b, mid, dst);
+}
+
+// Three fused steps per launch.  Step n on the tile plus a two-node ring
+// (68 x (TY+4)) from HBM into LDS, all loads issued up front; step n+1 on the
+// tile plus a one-node ring in place in LDS; step n+2 on the tile to HBM.
+// HBM traffic per update is a third of a single step's; the rings cost
+// (68 (TY+4) + 66 (TY+2) + 64 TY) / (3 * 64 TY) - 1 = 21 % extra collisions
+// at TY = 12 (FP32: 39 KB of LDS, four workgroups per CU) and 56 % at TY = 4
+// (FP64: 39 KB).
+template <typename S, int FM, bool SR, int TY>
+__global__ __launch_bounds__(256) void k_step3(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
+                                               uint32_t key_c) {
+  constexpr int H = 2, EW = 64 + 2 * H, EH = TY + 2 * H;
+  __shared__ S mid[9][EH][EW];
+  const auto rt = rates(a);
+  int x0, y0;
+  bool interior, fast;
+  tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
+  stage_from_hbm_prefetch<S, FM, SR, EH, EW>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  __syncthreads();
+  if (interior) {  // workgroup-uniform: every thread meets the same barriers
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 1>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_c, mid, dst);
+  } else {
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 1>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_c, mid, dst);
   }
 }
 
@@ -733,6 +912,32 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
     case 3:
       return a.stochastic ? launch_step2_fm<__bf16, true>(a.f, src, dst, key_a, key_b, st)
                           : launch_step2_fm<__bf16, false>(a.f, src, dst, key_a, key_b, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename S, bool SR>
+static hipError_t launch_step3_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                  uint32_t kb, uint32_t kc, hipStream_t st) {
+  const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
+  const dim3 grid((unsigned)(k.g.t3_tiles_x * k.g.t3_tiles_y));
+  constexpr int TY = sizeof(S) == 8 ? 4 : 12;
+  if (k.g.t3_ty != TY) return hipErrorInvalidValue;
+  if (fm == 0)
+    hipLaunchKernelGGL((k_step3<S, 0, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+  else if (fm == 1)
+    hipLaunchKernelGGL((k_step3<S, 1, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+  else
+    hipLaunchKernelGGL((k_step3<S, 2, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+  return hipGetLastError();
+}
+
+hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                        uint32_t key_c, hipStream_t st) {
+  // FP64 and FP32 only: the 16-bit modes run two steps per launch.
+  switch (a.storage) {
+    case 0: return launch_step3_fm<double, false>(a.d, src, dst, key_a, key_b, key_c, st);
+    case 1: return launch_step3_fm<float, false>(a.f, src, dst, key_a, key_b, key_c, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -22,8 +22,10 @@ struct Geom {
   uint32_t lattice_bytes;  // 9 * plane * sizeof(storage) (when fast)
   uint32_t ld_soff[9];
   uint32_t st_soff[9];
-  // Two-step kernel tiling: 64 x t2_ty output nodes per workgroup.
+  // Two- and three-step kernel tilings: 64 x t2_ty (t3_ty) output nodes per
+  // workgroup.
   int32_t t2_ty, t2_tiles_x, t2_tiles_y;
+  int32_t t3_ty, t3_tiles_x, t3_tiles_y;
 };
 
 // Kernel arguments in the compute real R.
@@ -60,6 +62,11 @@ hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t k
 // launch_step calls.
 hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                         hipStream_t st);
+// Three steps in one launch (FP64 and FP32 storage): src (state n) -> dst
+// (state n+3), keys of steps n, n+1, n+2.  Same result as three launch_step
+// calls.
+hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                        uint32_t key_c, hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);

@@ -189,7 +189,7 @@ def test_diagnostics_detect_instability():
     assert ei.value.status == _lib.LBM_EUNSTABLE
 
 
-# ------------------------------------------------- two-step (temporal) kernel
+# ------------------------------------------- multi-step (temporal) kernels
 
 @pytest.mark.parametrize("storage,rounding", [("fp64", "nearest"), ("fp32", "nearest"), ("fp16", "nearest"),
                                               ("bf16", "nearest"), ("fp16", "stochastic"),
@@ -197,9 +197,12 @@ def test_diagnostics_detect_instability():
 @pytest.mark.parametrize("shape", [(2, 2), (3, 200), (300, 5), (67, 33), (130, 70), (200, 131)])
 @pytest.mark.parametrize("bci", [0, 1, 3])
 @pytest.mark.parametrize("force", ["none", "uniform", "field"])
-def test_two_step_launch_equals_single_steps(storage, rounding, shape, bci, force):
-    """lbm_step(n) runs pairs of steps as one two-step launch (first step kept
-    in LDS); it must give bit-for-bit the state of n single-step launches."""
+@pytest.mark.parametrize("n", [5, 7])
+def test_multi_step_launch_equals_single_steps(storage, rounding, shape, bci, force, n):
+    """lbm_step(n) fuses steps in launches of three (FP64, FP32: 5 = 3 + 2,
+    7 = 3 + 3 + 1) or two (16-bit: 5 = 2 + 2 + 1, 7 = 2 + 2 + 2 + 1), the
+    intermediate states kept in LDS; it must give bit-for-bit the state of n
+    single-step launches."""
     from paper_1202_6351_amd import Lattice, Params
     nx, ny = shape
     bc, wu = BCS[bci]
@@ -210,10 +213,10 @@ def test_two_step_launch_equals_single_steps(storage, rounding, shape, bci, forc
         kw.update(fx=2e-5, fy=-1e-5)
     f0 = W.random_populations(nx, ny, seed=nx * 3 + ny, amp=0.05)
     a = Lattice(Params(nx, ny, **kw), device="cuda:0", force=None if frc is None else torch.from_numpy(frc))
-    a.set_populations(f0).step(5)
+    a.set_populations(f0).step(n)
     b = Lattice(Params(nx, ny, **kw), device="cuda:0", force=None if frc is None else torch.from_numpy(frc))
     b.set_populations(f0)
-    for _ in range(5):
-        b.step(1)  # an odd count always runs the single-step kernel
-    assert a.time == 5 and b.time == 5
+    for _ in range(n):
+        b.step(1)  # a count of one always runs the single-step kernel
+    assert a.time == n and b.time == n
     assert torch.equal(a.populations(), b.populations())
