@@ -120,7 +120,16 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
   g.t2_ty = storage_size(p->storage) == 8 ? 8 : 16;
   g.t2_tiles_x = (int32_t)((p->nx + 63) / 64);
   g.t2_tiles_y = (int32_t)((p->ny + g.t2_ty - 1) / g.t2_ty);
-  g.t3_ty = storage_size(p->storage) == 8 ? 4 : 12;
+  if (storage_size(p->storage) != 8) {
+    g.t3_ty = lbm::kStep3TyF32;
+    g.t3_threads = lbm::kStep3ThreadsF32;
+  } else if ((int64_t)p->nx * p->ny >= lbm::kStep3LargeMinNodes) {
+    g.t3_ty = lbm::kStep3TyF64Large;
+    g.t3_threads = lbm::kStep3ThreadsF64Large;
+  } else {
+    g.t3_ty = lbm::kStep3TyF64;
+    g.t3_threads = lbm::kStep3ThreadsF64;
+  }
   g.t3_tiles_x = g.t2_tiles_x;
   g.t3_tiles_y = (int32_t)((p->ny + g.t3_ty - 1) / g.t3_ty);
   a.w[0] = (R)p->omega3;

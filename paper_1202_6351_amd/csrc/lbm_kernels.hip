@@ -438,26 +438,26 @@ __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>
 // The same with every load of the thread's cells issued before the first
 // collision, so that HBM latency is paid once per stage rather than once per
 // cell.
-template <typename S, int FM, bool SR, int EH, int EW>
+template <typename S, int FM, bool SR, int EH, int EW, int NT>
 __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Codec<S>::R>& a,
                                                         const Rates<typename Codec<S>::R>& rt,
                                                         const S* __restrict__ src, int wx0, int wy0, bool fast,
                                                         uint32_t key, S (&mid)[9][EH][EW]) {
   using R = typename Codec<S>::R;
-  constexpr int NPT = (EW * EH + 255) / 256;
+  constexpr int NPT = (EW * EH + NT - 1) / NT;
   const __amdgpu_buffer_rsrc_t rs = rsrc(src, a.g.lattice_bytes);
   R d[NPT][9];
   int gx[NPT], gy[NPT];
   bool live[NPT];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int i = (int)threadIdx.x + 256 * j;
+    const int i = (int)threadIdx.x + NT * j;
     live[j] = i < EW * EH && window_node(a.g, wx0 + i % EW, wy0 + i / EW, gx[j], gy[j]);
     if (live[j]) pull_hbm<S>(a, rs, src, fast, gx[j], gy[j], d[j]);
   }
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int i = (int)threadIdx.x + 256 * j;
+    const int i = (int)threadIdx.x + NT * j;
     if (live[j]) collide_into_window<S, FM, SR, EH, EW>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW);
   }
 }
@@ -467,18 +467,18 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 // collides its cells into registers; after a barrier it writes them back.
 // WALLS = false: the window lies inside the domain and no cell's link
 // crosses a wall.
-template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING>
+template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT>
 __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
                                              uint32_t key, S (&mid)[9][EH][EW]) {
   using R = typename Codec<S>::R;
-  constexpr int RW = EW - 2 * (H - RING), RH = EH - 2 * (H - RING), NPT = (RW * RH + 255) / 256;
+  constexpr int RW = EW - 2 * (H - RING), RH = EH - 2 * (H - RING), NPT = (RW * RH + NT - 1) / NT;
   const Geom& g = a.g;
   S o[NPT][9];
   bool live[NPT];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int i = (int)threadIdx.x + 256 * j;
+    const int i = (int)threadIdx.x + NT * j;
     const int cx = H - RING + i % RW, cy = H - RING + i / RW;
     int gx = wx0 + cx, gy = wy0 + cy;
     live[j] = i < RW * RH && (!WALLS || window_node(g, wx0 + cx, wy0 + cy, gx, gy));
@@ -495,7 +495,7 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     if (!live[j]) continue;
-    const int i = (int)threadIdx.x + 256 * j;
+    const int i = (int)threadIdx.x + NT * j;
     const int cx = H - RING + i % RW, cy = H - RING + i / RW;
 #pragma unroll
     for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[j][k];
@@ -504,14 +504,14 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
 }
 
 // Last stage: one step on the 64 x TY tile from LDS to HBM.
-template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H>
+template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT>
 __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int x0, int y0,
                                              uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst) {
   using R = typename Codec<S>::R;
   const Geom& g = a.g;
   const int lx = (int)threadIdx.x & 63;
-  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += 4) {
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += NT / 64) {
     const int gx = x0 + lx, gy = y0 + ly;
     if (gx >= g.nx || gy >= g.ny) continue;
     R d[9];
@@ -565,9 +565,9 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
   stage_from_hbm<S, FM, SR, EH, EW>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
   if (interior)  // workgroup-uniform
-    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_b, mid, dst);
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, 256>(a, rt, x0, y0, key_b, mid, dst);
   else
-    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_b, mid, dst);
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, 256>(a, rt, x0, y0, key_b, mid, dst);
 }
 
 // Three fused steps per launch.  Step n on the tile plus a two-node ring
@@ -577,8 +577,8 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
 // (68 (TY+4) + 66 (TY+2) + 64 TY) / (3 * 64 TY) - 1 = 21 % extra collisions
 // at TY = 12 (FP32: 39 KB of LDS, four workgroups per CU) and 56 % at TY = 4
 // (FP64: 39 KB).
-template <typename S, int FM, bool SR, int TY>
-__global__ __launch_bounds__(256) void k_step3(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+template <typename S, int FM, bool SR, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
                                                S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
                                                uint32_t key_c) {
   constexpr int H = 2, EW = 64 + 2 * H, EH = TY + 2 * H;
@@ -587,14 +587,14 @@ __global__ __launch_bounds__(256) void k_step3(KArgs<typename Codec<S>::R> a, co
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  stage_from_hbm_prefetch<S, FM, SR, EH, EW>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
   if (interior) {  // workgroup-uniform: every thread meets the same barriers
-    stage_in_lds<false, S, FM, SR, EH, EW, H, 1>(a, rt, x0 - H, y0 - H, key_b, mid);
-    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_c, mid, dst);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
   } else {
-    stage_in_lds<true, S, FM, SR, EH, EW, H, 1>(a, rt, x0 - H, y0 - H, key_b, mid);
-    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H>(a, rt, x0, y0, key_c, mid, dst);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
   }
 }
 
@@ -916,19 +916,18 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
   }
 }
 
-template <typename S, bool SR>
+template <typename S, bool SR, int TY, int NT>
 static hipError_t launch_step3_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
                                   uint32_t kb, uint32_t kc, hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(k.g.t3_tiles_x * k.g.t3_tiles_y));
-  constexpr int TY = sizeof(S) == 8 ? 4 : 12;
-  if (k.g.t3_ty != TY) return hipErrorInvalidValue;
+  if (k.g.t3_ty != TY || k.g.t3_threads != NT) return hipErrorInvalidValue;
   if (fm == 0)
-    hipLaunchKernelGGL((k_step3<S, 0, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_step3<S, 0, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
   else if (fm == 1)
-    hipLaunchKernelGGL((k_step3<S, 1, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_step3<S, 1, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
   else
-    hipLaunchKernelGGL((k_step3<S, 2, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_step3<S, 2, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
   return hipGetLastError();
 }
 
@@ -936,8 +935,14 @@ hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t 
                         uint32_t key_c, hipStream_t st) {
   // FP64 and FP32 only: the 16-bit modes run two steps per launch.
   switch (a.storage) {
-    case 0: return launch_step3_fm<double, false>(a.d, src, dst, key_a, key_b, key_c, st);
-    case 1: return launch_step3_fm<float, false>(a.f, src, dst, key_a, key_b, key_c, st);
+    case 0:
+      return a.d.g.t3_threads == kStep3ThreadsF64Large
+                 ? launch_step3_fm<double, false, kStep3TyF64Large, kStep3ThreadsF64Large>(a.d, src, dst, key_a,
+                                                                                          key_b, key_c, st)
+                 : launch_step3_fm<double, false, kStep3TyF64, kStep3ThreadsF64>(a.d, src, dst, key_a, key_b,
+                                                                                key_c, st);
+    case 1:
+      return launch_step3_fm<float, false, kStep3TyF32, kStep3ThreadsF32>(a.f, src, dst, key_a, key_b, key_c, st);
     default: return hipErrorInvalidValue;
   }
 }

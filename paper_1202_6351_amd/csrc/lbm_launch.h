@@ -25,8 +25,17 @@ struct Geom {
   // Two- and three-step kernel tilings: 64 x t2_ty (t3_ty) output nodes per
   // workgroup.
   int32_t t2_ty, t2_tiles_x, t2_tiles_y;
-  int32_t t3_ty, t3_tiles_x, t3_tiles_y;
+  int32_t t3_ty, t3_tiles_x, t3_tiles_y, t3_threads;
 };
+
+// Three-step kernel shapes: output tile 64 x TY, NT threads per workgroup
+// (both at four workgroups' or two large workgroups' worth of LDS per CU).
+// FP64 takes the large shape, whose ring costs fewer recomputed nodes, once
+// the lattice has enough tiles of it to fill the chip.
+constexpr int kStep3TyF32 = 12, kStep3ThreadsF32 = 256;
+constexpr int kStep3TyF64 = 4, kStep3ThreadsF64 = 256;
+constexpr int kStep3TyF64Large = 10, kStep3ThreadsF64Large = 512;
+constexpr int64_t kStep3LargeMinNodes = 1 << 20;
 
 // Kernel arguments in the compute real R.
 template <typename R>

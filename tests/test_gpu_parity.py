@@ -220,3 +220,26 @@ def test_multi_step_launch_equals_single_steps(storage, rounding, shape, bci, fo
         b.step(1)  # a count of one always runs the single-step kernel
     assert a.time == n and b.time == n
     assert torch.equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("bci", [0, 1, 3])
+@pytest.mark.parametrize("force", ["none", "field"])
+def test_multi_step_launch_large_shape(storage, bci, force):
+    """Above a million nodes FP64 runs its three-step launch with the large
+    workgroup shape; 1030 x 1030 (ragged against every tile size), seven
+    steps, bit-for-bit seven single steps."""
+    from paper_1202_6351_amd import Lattice, Params
+    nx = ny = 1030
+    bc, wu = BCS[bci]
+    frc = W.force_field(nx, ny, 1e-4, seed=4) if force == "field" else None
+    kw = dict(tau=0.6, omega3=1.1, omega6=0.9, omega7=1.2, bc=bc, wall_u=wu, storage=storage)
+    f0 = W.random_populations(nx, ny, seed=11, amp=0.05)
+    mk = lambda: Lattice(Params(nx, ny, **kw), device="cuda:0",
+                         force=None if frc is None else torch.from_numpy(frc)).set_populations(f0)
+    a = mk().step(7)
+    b = mk()
+    for _ in range(7):
+        b.step(1)
+    assert torch.equal(a.populations(), b.populations())
+
