@@ -176,8 +176,10 @@ lbm_status lbm_get_populations(lbm_ctx* ctx, void* f);
 /* Advance n >= 0 steps (Sec. II stream-and-collide: per node raw moments,
  * central moments about u, relaxation of each central moment at its own
  * rate with central-moment forcing, back to populations; pull streaming with
- * the boundary rules).  One fused kernel launch per step, ping-pong between
- * lat0 and lat1. */
+ * the boundary rules).  Steps are fused per kernel launch, three at a time
+ * for LBM_FP64 and LBM_FP32 and two at a time for the 16-bit modes, with the
+ * intermediate states in on-chip memory; the result equals n single steps
+ * bit for bit.  Ping-pong between lat0 and lat1. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* One step from lattice buffer src (state n) into dst (state n+1), outside
@@ -185,6 +187,14 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
  * src != dst; both lattice buffers of this context's layout.  Does not change
  * lbm_time or the current lattice. */
 lbm_status lbm_step_between(lbm_ctx* ctx, const void* src, void* dst);
+
+/* n >= 0 single steps that keep every state: states[0] = step(src),
+ * states[i] = step(states[i-1]).  states: host array of n device lattice
+ * buffers of this context's layout, none equal to src or to its neighbour
+ * in the sequence (each step reads the previous buffer and writes the next).
+ * The segment recompute of a checkpointed adjoint.  Same result as n calls
+ * of lbm_step_between.  Does not change lbm_time or the current lattice. */
+lbm_status lbm_step_sequence(lbm_ctx* ctx, const void* src, void* const* states, int64_t n);
 
 /* Copy the current lattice to dst (snapshot) / src to the current lattice
  * (restore; also sets lbm_time to t).  Device lattice buffers. */
@@ -220,6 +230,17 @@ lbm_status lbm_diagnostics(lbm_ctx* ctx, double out[4]);
  * atomics).  LBM_EUNSUPPORTED for FP16/BF16 storage. */
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* lat_prev, const void* mu_in,
                             void* mu_out, void* grad_force);
+
+/* n >= 0 adjoint steps newest-first over one segment: states[0..n-1] are the
+ * lattice buffers of states k, k+1, ..., k+n-1 (host array of device
+ * pointers), mu_a holds the cotangent of state k+n on entry.  Step i =
+ * n-1 ... 0 applies lbm_adjoint_step(states[i], ...) and ping-pongs between
+ * mu_a and mu_b (distinct buffers in lattice layout), so that on return the
+ * cotangent of state k is in mu_a if n is even and in mu_b if n is odd.
+ * grad_force as for lbm_adjoint_step (every step ADDS its term).  Same result
+ * as n calls of lbm_adjoint_step.  LBM_EUNSUPPORTED for FP16/BF16 storage. */
+lbm_status lbm_adjoint_sequence(lbm_ctx* ctx, const void* const* states, int64_t n, void* mu_a,
+                                void* mu_b, void* grad_force);
 
 /* Adjoint of the macroscopic map at lattice buffer lat: given cotangents
  * g_rho, g_ux, g_uy (device R [ny][nx]; any may be NULL = 0) of rho, ux, uy,

@@ -57,11 +57,13 @@ SIGNATURES = {
     "lbm_get_populations": (_st, [_vp, _vp]),
     "lbm_step": (_st, [_vp, ctypes.c_int64]),
     "lbm_step_between": (_st, [_vp, _vp, _vp]),
+    "lbm_step_sequence": (_st, [_vp, _vp, ctypes.POINTER(_vp), ctypes.c_int64]),
     "lbm_snapshot": (_st, [_vp, _vp]),
     "lbm_restore": (_st, [_vp, _vp, ctypes.c_int64]),
     "lbm_macroscopic": (_st, [_vp] * 7),
     "lbm_diagnostics": (_st, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "lbm_adjoint_step": (_st, [_vp] * 5),
+    "lbm_adjoint_sequence": (_st, [_vp, ctypes.POINTER(_vp), ctypes.c_int64, _vp, _vp, _vp]),
     "lbm_adjoint_macroscopic": (_st, [_vp] * 7),
     "lbm_adjoint_init": (_st, [_vp] * 9),
 }
@@ -85,7 +87,7 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build the HIP library first "
-                "(python -m paper_1202_6351_amd.build, or __graft_entry__.build()).")
+                "(python paper_1202_6351_amd/build.py, or __graft_entry__.build()).")
         handle = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(handle, name)

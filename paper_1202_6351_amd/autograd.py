@@ -11,10 +11,13 @@ through each step in reverse (transposed per-node Jacobian of the cascaded
 collision and forcing, then reverse streaming), then through the
 initial-state map.
 
-Memory: the forward keeps a lattice snapshot every `checkpoint_every` steps;
-the backward recomputes each segment from its snapshot into a buffer of
-`checkpoint_every + 1` lattices and runs the adjoint over it newest-first.
-Work per step of the backward: one recomputed step and one adjoint step.
+Memory: the forward keeps a lattice snapshot every `checkpoint_every` steps.
+The backward recomputes each segment's states from its snapshot and runs the
+adjoint over them newest-first.  The recompute of the next (older) segment
+runs on a second stream while the adjoint of the current one runs, so the
+two kernels share the GPU; they alternate between two sets of
+`checkpoint_every - 1` lattice buffers.  Work per step of the backward: one
+recomputed step and one adjoint step.
 """
 from __future__ import annotations
 
@@ -70,21 +73,45 @@ class Rollout(torch.autograd.Function):
         g_ux = None if g_u is None else g_u[0].to(real).contiguous()
         g_uy = None if g_u is None else g_u[1].to(real).contiguous()
         mu, mu2 = lat.new_cotangent(), lat.new_cotangent()
-        nseg = len(ctx.snaps)
-        seg_len = [min(every, steps - s * every) for s in range(nseg)]
-        # Segment buffers: every node of seg[i] is written by the recompute
-        # before any read (row padding is never read), so no clearing.
-        bufs = [torch.empty_like(lat.lat[0]) for _ in range(min(every, max(steps, 0)))]
-        for s in range(nseg - 1, -1, -1):
-            n = max(seg_len[s], 0)
-            seg = [ctx.snaps[s]] + bufs[:n]
-            for i in range(1, n + 1):
-                lat.step_between(seg[i - 1], seg[i])
+        snaps = ctx.snaps
+        nseg = len(snaps)
+        seg_len = [max(min(every, steps - s * every), 0) for s in range(nseg)]
+        main = lat.stream
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(main)  # the snapshots are written on the main stream
+        # Recomputes run on `side` through a second context (same problem,
+        # same force field).  A segment of n steps needs its snapshot and the
+        # n - 1 states after it; the state after the last step of the last
+        # segment is the forward lattice's current state.
+        rec = Lattice(p, device=dev, force=lat.force, stream=side)
+        width = max(min(every, max(steps, 0)) - 1, 0)
+        sets = [[torch.empty_like(lat.lat[0]) for _ in range(width)] for _ in range(2)]
+        for t in [*snaps, *sets[0], *sets[1], lat.force]:
+            t.record_stream(side)
+        ready = [torch.cuda.Event(), torch.cuda.Event()]
+        free = [None, None]
+
+        def recompute(s, b):
+            if free[b] is not None:
+                side.wait_event(free[b])  # the adjoint that read this set is done
+            rec.step_sequence(snaps[s], sets[b][:max(seg_len[s] - 1, 0)])
+            ready[b].record(side)
+
+        recompute(nseg - 1, 0)
+        for k, s in enumerate(range(nseg - 1, -1, -1)):
+            b = k % 2
+            if s > 0:
+                recompute(s - 1, 1 - b)
+            main.wait_event(ready[b])
+            n = seg_len[s]
+            states = [snaps[s]] + sets[b][:max(n - 1, 0)]
             if s == nseg - 1:
-                lat.adjoint_macroscopic(seg[n], g_rho, g_ux, g_uy, mu, grad_force)
-            for i in range(n, 0, -1):
-                lat.adjoint_step(seg[i - 1], mu, mu2, grad_force)
+                lat.adjoint_macroscopic(lat.current, g_rho, g_ux, g_uy, mu, grad_force)
+            if lat.adjoint_sequence(states[:n], mu, mu2, grad_force) is mu2:
                 mu, mu2 = mu2, mu
+            free[b] = torch.cuda.Event()
+            free[b].record(main)
+        main.wait_stream(side)
         rho, ux0, uy0 = ctx.init_fields
         g_ux0 = torch.empty_like(ux0, dtype=real)
         g_uy0 = torch.empty_like(uy0, dtype=real)

@@ -1,6 +1,6 @@
 """Build liblbm.so (the HIP library behind include/lbm.h) for gfx950.
 
-    python -m paper_1202_6351_amd.build
+    python paper_1202_6351_amd/build.py
 
 Compiles every source under csrc/ with hipcc, in-tree, so the library ships
 with the package directory.  Packed FP32 instructions are disabled

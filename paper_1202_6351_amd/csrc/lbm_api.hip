@@ -326,6 +326,25 @@ lbm_status lbm_step_between(lbm_ctx* c, const void* src, void* dst) {
   return dev_err(c, lbm::launch_step(c->args, src, dst, step_key(c->p, c->t), c->stream), "step kernel");
 }
 
+lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, int64_t n) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0) return inval(c, "step_sequence: n < 0");
+  if (n > 0 && (!src || !states)) return inval(c, "step_sequence: need src and states");
+  for (int64_t i = 0; i < n; ++i) {
+    const void* prev = i == 0 ? src : states[i - 1];
+    if (!states[i] || states[i] == prev) return inval(c, "step_sequence: states[i] NULL or equal to its input");
+    if (!aligned(states[i])) return inval(c, "step_sequence: buffers must be 256-byte aligned");
+  }
+  if (n > 0 && !aligned(src)) return inval(c, "step_sequence: buffers must be 256-byte aligned");
+  for (int64_t i = 0; i < n; ++i) {
+    lbm_status s = dev_err(c, lbm::launch_step(c->args, i == 0 ? src : states[i - 1], states[i],
+                                               step_key(c->p, c->t), c->stream),
+                           "step kernel");
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_snapshot(lbm_ctx* c, void* dst) {
   if (!c) return LBM_EINVAL;
   if (!dst) return inval(c, "snapshot: dst is NULL");
@@ -385,6 +404,28 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* lat_prev, const void* mu_in,
   if (grad_force && !c->has_force_field) return inval(c, "adjoint_step: grad_force needs a bound force field");
   return dev_err(c, lbm::launch_adjoint_step(c->args, lat_prev, mu_in, mu_out, grad_force, c->stream),
                  "adjoint step kernel");
+}
+
+lbm_status lbm_adjoint_sequence(lbm_ctx* c, const void* const* states, int64_t n, void* mu_a, void* mu_b,
+                                void* grad_force) {
+  if (!c) return LBM_EINVAL;
+  if (c->p.storage != LBM_FP64 && c->p.storage != LBM_FP32) {
+    set_err(c->err, "adjoint needs FP64 or FP32 storage");
+    return LBM_EUNSUPPORTED;
+  }
+  if (n < 0) return inval(c, "adjoint_sequence: n < 0");
+  if (!mu_a || !mu_b || mu_a == mu_b) return inval(c, "adjoint_sequence: need distinct mu_a, mu_b");
+  if (n > 0 && !states) return inval(c, "adjoint_sequence: need states");
+  for (int64_t i = 0; i < n; ++i)
+    if (!states[i]) return inval(c, "adjoint_sequence: states[i] is NULL");
+  if (grad_force && !c->has_force_field) return inval(c, "adjoint_sequence: grad_force needs a bound force field");
+  void* mu[2] = {mu_a, mu_b};
+  for (int64_t i = n - 1, k = 0; i >= 0; --i, k ^= 1) {
+    lbm_status s = dev_err(c, lbm::launch_adjoint_step(c->args, states[i], mu[k], mu[k ^ 1], grad_force, c->stream),
+                           "adjoint step kernel");
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
 }
 
 lbm_status lbm_adjoint_macroscopic(lbm_ctx* c, const void* lat, const void* g_rho, const void* g_ux,

@@ -189,6 +189,15 @@ class Lattice:
         self._lattice_like(dst, "dst")
         self._check(_lib.lib().lbm_step_between(self._ctx, _ptr(src), _ptr(dst)))
 
+    def step_sequence(self, src: torch.Tensor, states: Sequence[torch.Tensor]):
+        """states[0] = step(src), states[i] = step(states[i-1]): a segment
+        recompute that keeps every state (one native call)."""
+        self._lattice_like(src, "src")
+        for t in states:
+            self._lattice_like(t, "states[i]")
+        arr = (ctypes.c_void_p * len(states))(*[t.data_ptr() for t in states])
+        self._check(_lib.lib().lbm_step_sequence(self._ctx, _ptr(src), arr, len(states)))
+
     def snapshot(self, dst: Optional[torch.Tensor] = None) -> torch.Tensor:
         dst = self.new_lattice() if dst is None else dst
         self._lattice_like(dst, "dst")
@@ -217,6 +226,15 @@ class Lattice:
     def adjoint_step(self, lat_prev, mu_in, mu_out, grad_force=None):
         self._check(_lib.lib().lbm_adjoint_step(self._ctx, _ptr(lat_prev), _ptr(mu_in), _ptr(mu_out),
                                                 _ptr(grad_force)))
+
+    def adjoint_sequence(self, states: Sequence[torch.Tensor], mu_a, mu_b, grad_force=None):
+        """Adjoint steps newest-first over states[0..n-1] (mu_a: cotangent of
+        the state after the last one).  Returns the buffer, mu_a or mu_b,
+        that holds the cotangent of states[0]."""
+        arr = (ctypes.c_void_p * len(states))(*[t.data_ptr() for t in states])
+        self._check(_lib.lib().lbm_adjoint_sequence(self._ctx, arr, len(states), _ptr(mu_a), _ptr(mu_b),
+                                                    _ptr(grad_force)))
+        return mu_a if len(states) % 2 == 0 else mu_b
 
     def adjoint_macroscopic(self, lat, g_rho, g_ux, g_uy, mu_out, grad_force=None):
         self._check(_lib.lib().lbm_adjoint_macroscopic(self._ctx, _ptr(lat), _ptr(g_rho), _ptr(g_ux),

@@ -291,3 +291,62 @@ def test_rollout_fp32_gradient_close_to_fp64():
         rel = np.abs(a - b).sum() / np.abs(b).sum()
         print(f"fp32 vs fp64 gradient {k}: rel {rel:.3e}")
         assert rel < 1e-4
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [0, 1, 4, 7])
+def test_sequences_equal_single_calls(storage, n):
+    """lbm_step_sequence = n lbm_step_between calls, and lbm_adjoint_sequence
+    = n lbm_adjoint_step calls newest-first (result in mu_a for even n, mu_b
+    for odd n; grad_force accumulated by every step), bit for bit."""
+    nx, ny = 67, 33
+    bc, wu = BCS[2]
+    frc = W.force_field(nx, ny, 1e-4, seed=6)
+    lat = _lattice(nx, ny, frc, storage=storage, tau=0.7, omega3=1.1, bc=bc, wall_u=wu)
+    lat.set_populations(W.random_populations(nx, ny, seed=8, amp=0.05))
+    src = lat.snapshot()
+    seq = [lat.new_lattice() for _ in range(n)]
+    lat.step_sequence(src, seq)
+    prev = src
+    for i in range(n):
+        one = _step(lat, prev)
+        assert torch.equal(one, seq[i])
+        prev = one
+    states = [src] + seq[:-1] if n else []
+    mu0 = _lattice_noise(lat, 3).to(lat.real)
+    gf_a = torch.zeros(2, ny, nx, dtype=lat.real, device=DEV)
+    gf_b = torch.zeros_like(gf_a)
+    a, b = mu0.clone(), lat.new_cotangent()
+    res = lat.adjoint_sequence(states, a, b, gf_a)
+    assert res is (a if n % 2 == 0 else b)
+    mu, tmp = mu0.clone(), lat.new_cotangent()
+    for i in range(n - 1, -1, -1):
+        lat.adjoint_step(states[i], mu, tmp, gf_b)
+        mu, tmp = tmp, mu
+    assert torch.equal(res, mu)
+    assert torch.equal(gf_a, gf_b)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("T", [0, 1, 10, 23])
+def test_rollout_gradient_independent_of_checkpointing(storage, T):
+    """The backward pipeline (segment recompute on a second stream, two
+    alternating buffer sets) gives bit-for-bit the same gradients for every
+    checkpoint interval, ragged last segments included."""
+    from paper_1202_6351_amd import Params, rollout
+    nx, ny = 40, 24
+    bc, wu = BCS[1]
+    p = Params(nx, ny, tau=0.7, bc=bc, wall_u=wu, storage=storage)
+    real = p.real_dtype
+    F0 = torch.from_numpy(W.force_field(nx, ny, 1e-4, seed=9)).to(DEV, real)
+    u00 = torch.from_numpy(np.stack(W.random_flow(nx, ny, seed=5, u_amp=0.03)[1:])).to(DEV, real)
+    w = torch.from_numpy(np.random.default_rng(2).normal(size=(2, ny, nx))).to(DEV, real)
+    grads = []
+    for every in (1, 2, 3, 7, 10, 11, 40):
+        F = F0.clone().requires_grad_(True)
+        u0 = u00.clone().requires_grad_(True)
+        rho, u = rollout(p, F, u0, T, checkpoint_every=every)
+        ((u * w).sum() + rho.sum()).backward()
+        grads.append((F.grad.clone(), u0.grad.clone()))
+    for gF, gu in grads[1:]:
+        assert torch.equal(gF, grads[0][0]) and torch.equal(gu, grads[0][1])
