@@ -15,11 +15,14 @@
 // term; walls are resolved per thread from (x, y) with selects, so there is
 // no mask array and the wall rows do not diverge from the interior.
 //
-// Launch shape: 256-thread blocks covering TX x (256/TX) nodes, TX in
-// {64, 128, 256} (a 64-wide wavefront spans one row segment); the 1-D block
-// index is remapped so that each of the 8 XCDs (blocks are dealt to XCDs
-// round-robin) processes one contiguous band of tiles, keeping the lines
-// shared between horizontally and vertically adjacent tiles in one L2.
+// Launch shape of the single step: 256-thread blocks covering TX x (256/TX)
+// nodes, TX in {64, 128, 256} (a 64-wide wavefront spans one row segment).
+// The fused launches (k_step2, k_step3) give each workgroup a 64 x TY tile
+// and keep the intermediate steps of the tile and a recompute ring in LDS,
+// so the state crosses HBM once per two or three steps.  In every kernel the
+// 1-D block index is remapped so that each of the 8 XCDs (blocks are dealt
+// to XCDs round-robin) processes one contiguous band of tiles, keeping the
+// lines shared between horizontally and vertically adjacent tiles in one L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
