@@ -1,15 +1,20 @@
-"""Full-size GPU parity on sampled nodes, in the launch configuration the
-benchmark times (the library picks tiles and paths by lattice size).
+"""Full-size GPU parity on sampled nodes, at the sizes the benchmark runs
+(the library picks tiles and paths by lattice size).
 
 After a few hundred steps from the benchmark's initial state, the state f(n)
-is read back, one more step is taken on the GPU, and the oracle recomputes
-that step at sampled nodes (random interior nodes, every corner, nodes on
-every wall and wrap edge) from the same f(n).  The oracle works in FP64 from
-the values the GPU actually stored, so the difference is the GPU's own
-arithmetic and storage rounding for one step:
+is read back, one more step is taken on the GPU (the single-step kernel), and
+the oracle recomputes that step at sampled nodes (random interior nodes,
+every corner, nodes on every wall and wrap edge) from the same f(n).  The
+oracle works in FP64 from the values the GPU actually stored, so the
+difference is the GPU's own arithmetic and storage rounding for one step:
   FP64   <= 2e-15 absolute,
   FP32   <= 1e-7 absolute (FP32 arithmetic on deviations of order 1e-2),
   16-bit <= half an ulp of the stored deviation + 1e-7 (round to nearest).
+
+The launch the benchmark times fuses steps (three per launch in FP32 and
+FP64, two in 16-bit).  At the same sizes, one fused launch is checked against
+single steps bit for bit on the raw lattice buffers, and for FP32/FP64 a
+three-step launch from a read-back state against three full oracle steps.
 """
 import numpy as np
 import pytest
@@ -96,3 +101,56 @@ def test_beyond_fast_path_limit_sampled():
     lat.init_equilibrium(*W.at_rest(nx, ny, density_noise=1e-6, seed=3))
     p = oracle.Params(nx, ny, tau=0.7, fx=1e-6, bc=(0, 0, 1, 1), wall_u=(0, 0, 0, 0.05))
     _check_one_step(lat, p, "fp32", 20, seed=3)
+
+
+def _fused_equals_single(lat, group):
+    """One fused launch of `group` steps = `group` single-step launches, bit
+    for bit, on the raw lattice buffer."""
+    snap = lat.snapshot()
+    t = lat.time
+    lat.step(group)
+    fused = lat.current.clone()
+    lat.restore(snap, t)
+    for _ in range(group):
+        lat.step(1)
+    assert torch.equal(fused, lat.current)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 4e-7), ("fp64", 6e-15)])
+def test_cavity_4096_three_step_launch(storage, tol):
+    """The benchmark's launch: FP32 (and FP64) cavity 4096^2, Re 1000, three
+    steps in one launch after 300 warm-up steps.  Bit-exact against three
+    single steps; at sampled nodes within tol of three FP64 oracle steps from
+    the same read-back state (FP32: three steps of FP32 rounding)."""
+    from paper_1202_6351_amd import Lattice, Params
+    n = 4096
+    tau = W.cavity_tau(n, 0.1, 1000.0)
+    lat = Lattice(Params(n, n, tau=tau, bc=("wall",) * 4, wall_u=(0, 0, 0, 0.1), storage=storage),
+                  device="cuda:0")
+    lat.init_equilibrium(*W.at_rest(n, n, density_noise=1e-6, seed=2))
+    lat.step(300)
+    _fused_equals_single(lat, 3)
+    f_n = lat.populations().cpu().numpy()
+    lat.step(3)
+    p = oracle.Params(n, n, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
+    want_all = oracle.step(p, f_n, 3)
+    del f_n
+    xs, ys = _sample_nodes(n, n, 3000, seed=5)
+    got = lat.populations()[:, torch.from_numpy(ys).long().cuda(), torch.from_numpy(xs).long().cuda()].cpu().numpy()
+    want = want_all[:, ys, xs]
+    err = np.abs(got - want)
+    print(f"{storage} 4096x4096: max three-step error {err.max():.3e} over {len(xs)} nodes")
+    assert err.max() <= tol
+
+
+@pytest.mark.parametrize("storage,rounding", [("fp16", "nearest"), ("bf16", "stochastic")])
+def test_taylor_green_8192_two_step_launch(storage, rounding):
+    """The 16-bit forms' launch (two steps, Taylor-Green 8192^2) equals two
+    single steps bit for bit, stochastic keys included."""
+    from paper_1202_6351_amd import Lattice, Params
+    n = 8192
+    lat = Lattice(Params(n, n, tau=0.8, storage=storage, rounding=rounding, seed=1), device="cuda:0")
+    lat.init_equilibrium(*W.taylor_green(n, 0.05, noise=1e-5, seed=0))
+    lat.step(20)
+    _fused_equals_single(lat, 2)
+
