@@ -188,12 +188,14 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
  * lbm_time or the current lattice. */
 lbm_status lbm_step_between(lbm_ctx* ctx, const void* src, void* dst);
 
-/* n >= 0 single steps that keep every state: states[0] = step(src),
+/* n >= 0 steps that keep every state: states[0] = step(src),
  * states[i] = step(states[i-1]).  states: host array of n device lattice
- * buffers of this context's layout, none equal to src or to its neighbour
- * in the sequence (each step reads the previous buffer and writes the next).
- * The segment recompute of a checkpointed adjoint.  Same result as n calls
- * of lbm_step_between.  Does not change lbm_time or the current lattice. */
+ * buffers of this context's layout, 256-byte aligned, none equal to src and
+ * any four consecutive ones distinct.  For LBM_FP64 and LBM_FP32, groups of
+ * three run as one fused launch that stores both intermediate states as
+ * well.  The segment recompute of a checkpointed adjoint.  Same result as n
+ * calls of lbm_step_between (bit for bit).  Does not change lbm_time or the
+ * current lattice. */
 lbm_status lbm_step_sequence(lbm_ctx* ctx, const void* src, void* const* states, int64_t n);
 
 /* Copy the current lattice to dst (snapshot) / src to the current lattice

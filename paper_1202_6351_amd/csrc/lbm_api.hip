@@ -294,7 +294,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   for (; group == 3 && left >= 3; left -= 3) {
     lbm_status s = dev_err(c, lbm::launch_step3(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
                                                 step_key(c->p, c->t), step_key(c->p, c->t + 1),
-                                                step_key(c->p, c->t + 2), c->stream),
+                                                step_key(c->p, c->t + 2), nullptr, nullptr, c->stream),
                            "three-step kernel");
     if (s != LBM_OK) return s;
     c->cur ^= 1;
@@ -330,13 +330,27 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
   if (!c) return LBM_EINVAL;
   if (n < 0) return inval(c, "step_sequence: n < 0");
   if (n > 0 && (!src || !states)) return inval(c, "step_sequence: need src and states");
-  for (int64_t i = 0; i < n; ++i) {
-    const void* prev = i == 0 ? src : states[i - 1];
-    if (!states[i] || states[i] == prev) return inval(c, "step_sequence: states[i] NULL or equal to its input");
-    if (!aligned(states[i])) return inval(c, "step_sequence: buffers must be 256-byte aligned");
-  }
   if (n > 0 && !aligned(src)) return inval(c, "step_sequence: buffers must be 256-byte aligned");
   for (int64_t i = 0; i < n; ++i) {
+    if (!states[i] || states[i] == src) return inval(c, "step_sequence: states[i] NULL or equal to src");
+    if (!aligned(states[i])) return inval(c, "step_sequence: buffers must be 256-byte aligned");
+    // a fused launch reads one buffer and writes the next three: neighbours
+    // within three places must differ
+    for (int64_t k = i + 1; k < n && k <= i + 3; ++k)
+      if (states[k] == states[i]) return inval(c, "step_sequence: states must be distinct buffers");
+  }
+  // Groups of three run as one three-step launch that also stores the two
+  // intermediate states (FP64, FP32); the rest as single steps.
+  const bool fused = steps_per_launch(c->p.storage) == 3;
+  int64_t i = 0;
+  for (; fused && i + 3 <= n; i += 3) {
+    lbm_status s = dev_err(c, lbm::launch_step3(c->args, i == 0 ? src : states[i - 1], states[i + 2],
+                                                step_key(c->p, c->t), step_key(c->p, c->t), step_key(c->p, c->t),
+                                                states[i], states[i + 1], c->stream),
+                           "three-step kernel");
+    if (s != LBM_OK) return s;
+  }
+  for (; i < n; ++i) {
     lbm_status s = dev_err(c, lbm::launch_step(c->args, i == 0 ? src : states[i - 1], states[i],
                                                step_key(c->p, c->t), c->stream),
                            "step kernel");

@@ -383,22 +383,44 @@ __device__ __forceinline__ void force_at(const KArgs<R>& a, int gx, int gy, R& F
   }
 }
 
+// Stores of one node's nine stored values (non-temporal; buffer path when
+// the lattice is below 4 GiB).
+template <typename S>
+__device__ __forceinline__ void store_node(const Geom& g, S* __restrict__ dst, int gx, int gy, const S o[9]) {
+  if (g.fast) {
+    const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
+    const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], o[k]);
+  } else {
+    const int64_t c = (int64_t)gy * g.pitch + gx;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
+  }
+}
+
 // Step n for one window cell from its nine pulled populations d, rounded and
-// kept in LDS.
+// kept in LDS (and returned in o).
 template <typename S, int FM, bool SR, int EH, int EW>
 __device__ __forceinline__ void collide_into_window(const KArgs<typename Codec<S>::R>& a,
                                                     const Rates<typename Codec<S>::R>& rt, int gx, int gy,
                                                     const typename Codec<S>::R d[9], uint32_t key,
-                                                    S (&mid)[9][EH][EW], int cx, int cy) {
+                                                    S (&mid)[9][EH][EW], int cx, int cy, S o[9]) {
   using R = typename Codec<S>::R;
   R Fx, Fy;
   force_at<FM>(a, gx, gy, Fx, Fy);
   R out[9];
   collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
-  S o[9];
   round_out<S, SR>(out, (uint32_t)(gy * a.g.nx + gx), key, o);
 #pragma unroll
   for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[k];
+}
+
+// Window cell (cx, cy) of a window with an H-node ring around the 64 x TY
+// tile at (x0, y0): is it a node of the tile inside the domain?
+template <int H, int TY>
+__device__ __forceinline__ bool tile_cell(const Geom& g, int x0, int y0, int cx, int cy) {
+  return cx >= H && cx < H + 64 && cy >= H && cy < H + TY && x0 + cx - H < g.nx && y0 + cy - H < g.ny;
 }
 
 // Pull of window cell (gx, gy) for the first stage: from HBM, through the
@@ -434,18 +456,21 @@ __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>
     if (!window_node(a.g, wx0 + cx, wy0 + cy, gx, gy)) continue;
     R d[9];
     pull_hbm<S>(a, rs, src, fast, gx, gy, d);
-    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx, gy, d, key, mid, cx, cy);
+    S o[9];
+    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx, gy, d, key, mid, cx, cy, o);
   }
 }
 
 // The same with every load of the thread's cells issued before the first
 // collision, so that HBM latency is paid once per stage rather than once per
-// cell.
-template <typename S, int FM, bool SR, int EH, int EW, int NT>
+// cell.  KEEP: the tile's own cells (the 64 x TY tile inside an H-node ring)
+// are also stored to `keep`, the state after this step.
+template <typename S, int FM, bool SR, int EH, int EW, int NT, bool KEEP = false, int H = 0, int TY = 0>
 __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Codec<S>::R>& a,
                                                         const Rates<typename Codec<S>::R>& rt,
                                                         const S* __restrict__ src, int wx0, int wy0, bool fast,
-                                                        uint32_t key, S (&mid)[9][EH][EW]) {
+                                                        uint32_t key, S (&mid)[9][EH][EW],
+                                                        S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
   constexpr int NPT = (EW * EH + NT - 1) / NT;
   const __amdgpu_buffer_rsrc_t rs = rsrc(src, a.g.lattice_bytes);
@@ -461,7 +486,10 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int i = (int)threadIdx.x + NT * j;
-    if (live[j]) collide_into_window<S, FM, SR, EH, EW>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW);
+    if (!live[j]) continue;
+    S o[9];
+    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW, o);
+    if (KEEP && tile_cell<H, TY>(a.g, wx0 + H, wy0 + H, i % EW, i / EW)) store_node<S>(a.g, keep, gx[j], gy[j], o);
   }
 }
 
@@ -469,11 +497,13 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 // outside the tile (the window has an H-node ring).  Every thread pulls and
 // collides its cells into registers; after a barrier it writes them back.
 // WALLS = false: the window lies inside the domain and no cell's link
-// crosses a wall.
-template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT>
+// crosses a wall.  KEEP: the tile's own cells (tile height TY) are also
+// stored to `keep`, the state after this step.
+template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool KEEP = false,
+          int TY = 0>
 __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
-                                             uint32_t key, S (&mid)[9][EH][EW]) {
+                                             uint32_t key, S (&mid)[9][EH][EW], S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
   constexpr int RW = EW - 2 * (H - RING), RH = EH - 2 * (H - RING), NPT = (RW * RH + NT - 1) / NT;
   const Geom& g = a.g;
@@ -502,6 +532,7 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
     const int cx = H - RING + i % RW, cy = H - RING + i / RW;
 #pragma unroll
     for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[j][k];
+    if (KEEP && tile_cell<H, TY>(g, wx0 + H, wy0 + H, cx, cy)) store_node<S>(g, keep, wx0 + cx, wy0 + cy, o[j]);
   }
   __syncthreads();
 }
@@ -578,25 +609,30 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
 // tile plus a one-node ring in place in LDS; step n+2 on the tile to HBM.
 // HBM traffic per update is a third of a single step's; the rings cost
 // (68 (TY+4) + 66 (TY+2) + 64 TY) / (3 * 64 TY) - 1 = 21 % extra collisions
-// at TY = 12 (FP32: 39 KB of LDS, four workgroups per CU) and 56 % at TY = 4
-// (FP64: 39 KB).
-template <typename S, int FM, bool SR, int TY, int NT>
+// at TY = 12 (FP32: 39 KB of LDS, four workgroups per CU), 24 % at TY = 10
+// with 512 threads (FP64 above 2^20 nodes: 68.5 KB, two workgroups per CU)
+// and 56 % at TY = 4 (smaller FP64 lattices: 39 KB).
+//
+// KEEP: the states after the first and the second step are also stored, to
+// keep_a and keep_b (a segment recompute that keeps every state).
+template <typename S, int FM, bool SR, int TY, int NT, bool KEEP>
 __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
-                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
-                                               uint32_t key_c) {
+                                              S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
+                                              uint32_t key_c, S* __restrict__ keep_a, S* __restrict__ keep_b) {
   constexpr int H = 2, EW = 64 + 2 * H, EH = TY + 2 * H;
   __shared__ S mid[9][EH][EW];
   const auto rt = rates(a);
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, KEEP, H, TY>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid,
+                                                                keep_a);
   __syncthreads();
   if (interior) {  // workgroup-uniform: every thread meets the same barriers
-    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT, KEEP, TY>(a, rt, x0 - H, y0 - H, key_b, mid, keep_b);
     stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
   } else {
-    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT, KEEP, TY>(a, rt, x0 - H, y0 - H, key_b, mid, keep_b);
     stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
   }
 }
@@ -919,33 +955,47 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
   }
 }
 
-template <typename S, bool SR, int TY, int NT>
-static hipError_t launch_step3_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                                  uint32_t kb, uint32_t kc, hipStream_t st) {
+template <typename S, bool SR, int TY, int NT, bool KEEP>
+static hipError_t launch_step3_keep(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                    uint32_t kb, uint32_t kc, void* keep_a, void* keep_b, hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(k.g.t3_tiles_x * k.g.t3_tiles_y));
   if (k.g.t3_ty != TY || k.g.t3_threads != NT) return hipErrorInvalidValue;
+  S* const a = (S*)keep_a;
+  S* const b = (S*)keep_b;
   if (fm == 0)
-    hipLaunchKernelGGL((k_step3<S, 0, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_step3<S, 0, SR, TY, NT, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
+                       kc, a, b);
   else if (fm == 1)
-    hipLaunchKernelGGL((k_step3<S, 1, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_step3<S, 1, SR, TY, NT, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
+                       kc, a, b);
   else
-    hipLaunchKernelGGL((k_step3<S, 2, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_step3<S, 2, SR, TY, NT, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
+                       kc, a, b);
   return hipGetLastError();
 }
 
+template <typename S, bool SR, int TY, int NT>
+static hipError_t launch_step3_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                  uint32_t kb, uint32_t kc, void* keep_a, void* keep_b, hipStream_t st) {
+  if ((keep_a == nullptr) != (keep_b == nullptr)) return hipErrorInvalidValue;
+  return keep_a ? launch_step3_keep<S, SR, TY, NT, true>(k, src, dst, ka, kb, kc, keep_a, keep_b, st)
+                : launch_step3_keep<S, SR, TY, NT, false>(k, src, dst, ka, kb, kc, nullptr, nullptr, st);
+}
+
 hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
-                        uint32_t key_c, hipStream_t st) {
+                        uint32_t key_c, void* keep_a, void* keep_b, hipStream_t st) {
   // FP64 and FP32 only: the 16-bit modes run two steps per launch.
   switch (a.storage) {
     case 0:
       return a.d.g.t3_threads == kStep3ThreadsF64Large
-                 ? launch_step3_fm<double, false, kStep3TyF64Large, kStep3ThreadsF64Large>(a.d, src, dst, key_a,
-                                                                                          key_b, key_c, st)
-                 : launch_step3_fm<double, false, kStep3TyF64, kStep3ThreadsF64>(a.d, src, dst, key_a, key_b,
-                                                                                key_c, st);
+                 ? launch_step3_fm<double, false, kStep3TyF64Large, kStep3ThreadsF64Large>(
+                       a.d, src, dst, key_a, key_b, key_c, keep_a, keep_b, st)
+                 : launch_step3_fm<double, false, kStep3TyF64, kStep3ThreadsF64>(a.d, src, dst, key_a, key_b, key_c,
+                                                                                keep_a, keep_b, st);
     case 1:
-      return launch_step3_fm<float, false, kStep3TyF32, kStep3ThreadsF32>(a.f, src, dst, key_a, key_b, key_c, st);
+      return launch_step3_fm<float, false, kStep3TyF32, kStep3ThreadsF32>(a.f, src, dst, key_a, key_b, key_c,
+                                                                          keep_a, keep_b, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -73,9 +73,10 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
                         hipStream_t st);
 // Three steps in one launch (FP64 and FP32 storage): src (state n) -> dst
 // (state n+3), keys of steps n, n+1, n+2.  Same result as three launch_step
-// calls.
+// calls.  keep_a, keep_b: both NULL, or buffers that also receive states
+// n+1 and n+2.
 hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
-                        uint32_t key_c, hipStream_t st);
+                        uint32_t key_c, void* keep_a, void* keep_b, hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);

@@ -294,7 +294,7 @@ def test_rollout_fp32_gradient_close_to_fp64():
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [0, 1, 4, 7])
+@pytest.mark.parametrize("n", [0, 1, 4, 6, 7])
 def test_sequences_equal_single_calls(storage, n):
     """lbm_step_sequence = n lbm_step_between calls, and lbm_adjoint_sequence
     = n lbm_adjoint_step calls newest-first (result in mu_a for even n, mu_b
@@ -350,3 +350,23 @@ def test_rollout_gradient_independent_of_checkpointing(storage, T):
         grads.append((F.grad.clone(), u0.grad.clone()))
     for gF, gu in grads[1:]:
         assert torch.equal(gF, grads[0][0]) and torch.equal(gu, grads[0][1])
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_step_sequence_large_shape(storage):
+    """lbm_step_sequence on 1030 x 1030 (FP64 takes its large three-step
+    shape there), walls and lid, force field: seven kept states equal seven
+    lbm_step_between calls bit for bit."""
+    nx = ny = 1030
+    bc, wu = BCS[2]
+    lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=12), storage=storage, tau=0.6, bc=bc, wall_u=wu)
+    lat.set_populations(W.random_populations(nx, ny, seed=13, amp=0.05))
+    src = lat.snapshot()
+    seq = [lat.new_lattice() for _ in range(7)]
+    lat.step_sequence(src, seq)
+    prev = src
+    for i in range(7):
+        one = _step(lat, prev)
+        assert torch.equal(one, seq[i]), i
+        prev = one
+
