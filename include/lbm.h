@@ -188,14 +188,12 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
  * lbm_time or the current lattice. */
 lbm_status lbm_step_between(lbm_ctx* ctx, const void* src, void* dst);
 
-/* n >= 0 steps that keep every state: states[0] = step(src),
+/* n >= 0 single steps that keep every state: states[0] = step(src),
  * states[i] = step(states[i-1]).  states: host array of n device lattice
- * buffers of this context's layout, 256-byte aligned, none equal to src and
- * any four consecutive ones distinct.  For LBM_FP64 and LBM_FP32, groups of
- * three run as one fused launch that stores both intermediate states as
- * well.  The segment recompute of a checkpointed adjoint.  Same result as n
- * calls of lbm_step_between (bit for bit).  Does not change lbm_time or the
- * current lattice. */
+ * buffers of this context's layout, 256-byte aligned, none equal to its
+ * input (src for states[0], states[i-1] for states[i]).  The segment
+ * recompute of a checkpointed adjoint.  Same result as n calls of
+ * lbm_step_between.  Does not change lbm_time or the current lattice. */
 lbm_status lbm_step_sequence(lbm_ctx* ctx, const void* src, void* const* states, int64_t n);
 
 /* Copy the current lattice to dst (snapshot) / src to the current lattice
@@ -235,14 +233,17 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* lat_prev, const void* mu_i
 
 /* n >= 0 adjoint steps newest-first over one segment: states[0..n-1] are the
  * lattice buffers of states k, k+1, ..., k+n-1 (host array of device
- * pointers), mu_a holds the cotangent of state k+n on entry.  Step i =
- * n-1 ... 0 applies lbm_adjoint_step(states[i], ...) and ping-pongs between
- * mu_a and mu_b (distinct buffers in lattice layout), so that on return the
- * cotangent of state k is in mu_a if n is even and in mu_b if n is odd.
- * grad_force as for lbm_adjoint_step (every step ADDS its term).  Same result
- * as n calls of lbm_adjoint_step.  LBM_EUNSUPPORTED for FP16/BF16 storage. */
+ * pointers), mu_a holds the cotangent of state k+n on entry.  The steps run
+ * in pairs fused in one launch (the intermediate cotangent stays in
+ * on-chip memory), an odd one alone, ping-ponging between mu_a and mu_b
+ * (distinct buffers in lattice layout).  On return *result_in_b (host int)
+ * is 0 if the cotangent of state k is in mu_a and 1 if it is in mu_b; the
+ * other buffer is scratch.  grad_force as for lbm_adjoint_step (every step
+ * ADDS its term, in the same order as single calls).  Same result as n calls
+ * of lbm_adjoint_step, bit for bit.  LBM_EUNSUPPORTED for FP16/BF16
+ * storage. */
 lbm_status lbm_adjoint_sequence(lbm_ctx* ctx, const void* const* states, int64_t n, void* mu_a,
-                                void* mu_b, void* grad_force);
+                                void* mu_b, void* grad_force, int* result_in_b);
 
 /* Adjoint of the macroscopic map at lattice buffer lat: given cotangents
  * g_rho, g_ux, g_uy (device R [ny][nx]; any may be NULL = 0) of rho, ux, uy,

@@ -63,7 +63,8 @@ SIGNATURES = {
     "lbm_macroscopic": (_st, [_vp] * 7),
     "lbm_diagnostics": (_st, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "lbm_adjoint_step": (_st, [_vp] * 5),
-    "lbm_adjoint_sequence": (_st, [_vp, ctypes.POINTER(_vp), ctypes.c_int64, _vp, _vp, _vp]),
+    "lbm_adjoint_sequence": (_st, [_vp, ctypes.POINTER(_vp), ctypes.c_int64, _vp, _vp, _vp,
+                                   ctypes.POINTER(ctypes.c_int)]),
     "lbm_adjoint_macroscopic": (_st, [_vp] * 7),
     "lbm_adjoint_init": (_st, [_vp] * 9),
 }

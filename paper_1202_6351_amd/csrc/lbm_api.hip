@@ -294,7 +294,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   for (; group == 3 && left >= 3; left -= 3) {
     lbm_status s = dev_err(c, lbm::launch_step3(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
                                                 step_key(c->p, c->t), step_key(c->p, c->t + 1),
-                                                step_key(c->p, c->t + 2), nullptr, nullptr, c->stream),
+                                                step_key(c->p, c->t + 2), c->stream),
                            "three-step kernel");
     if (s != LBM_OK) return s;
     c->cur ^= 1;
@@ -332,25 +332,11 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
   if (n > 0 && (!src || !states)) return inval(c, "step_sequence: need src and states");
   if (n > 0 && !aligned(src)) return inval(c, "step_sequence: buffers must be 256-byte aligned");
   for (int64_t i = 0; i < n; ++i) {
-    if (!states[i] || states[i] == src) return inval(c, "step_sequence: states[i] NULL or equal to src");
+    const void* prev = i == 0 ? src : states[i - 1];
+    if (!states[i] || states[i] == prev) return inval(c, "step_sequence: states[i] NULL or equal to its input");
     if (!aligned(states[i])) return inval(c, "step_sequence: buffers must be 256-byte aligned");
-    // a fused launch reads one buffer and writes the next three: neighbours
-    // within three places must differ
-    for (int64_t k = i + 1; k < n && k <= i + 3; ++k)
-      if (states[k] == states[i]) return inval(c, "step_sequence: states must be distinct buffers");
   }
-  // Groups of three run as one three-step launch that also stores the two
-  // intermediate states (FP64, FP32); the rest as single steps.
-  const bool fused = steps_per_launch(c->p.storage) == 3;
-  int64_t i = 0;
-  for (; fused && i + 3 <= n; i += 3) {
-    lbm_status s = dev_err(c, lbm::launch_step3(c->args, i == 0 ? src : states[i - 1], states[i + 2],
-                                                step_key(c->p, c->t), step_key(c->p, c->t), step_key(c->p, c->t),
-                                                states[i], states[i + 1], c->stream),
-                           "three-step kernel");
-    if (s != LBM_OK) return s;
-  }
-  for (; i < n; ++i) {
+  for (int64_t i = 0; i < n; ++i) {
     lbm_status s = dev_err(c, lbm::launch_step(c->args, i == 0 ? src : states[i - 1], states[i],
                                                step_key(c->p, c->t), c->stream),
                            "step kernel");
@@ -421,7 +407,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* lat_prev, const void* mu_in,
 }
 
 lbm_status lbm_adjoint_sequence(lbm_ctx* c, const void* const* states, int64_t n, void* mu_a, void* mu_b,
-                                void* grad_force) {
+                                void* grad_force, int* result_in_b) {
   if (!c) return LBM_EINVAL;
   if (c->p.storage != LBM_FP64 && c->p.storage != LBM_FP32) {
     set_err(c->err, "adjoint needs FP64 or FP32 storage");
@@ -429,16 +415,28 @@ lbm_status lbm_adjoint_sequence(lbm_ctx* c, const void* const* states, int64_t n
   }
   if (n < 0) return inval(c, "adjoint_sequence: n < 0");
   if (!mu_a || !mu_b || mu_a == mu_b) return inval(c, "adjoint_sequence: need distinct mu_a, mu_b");
+  if (!result_in_b) return inval(c, "adjoint_sequence: result_in_b is NULL");
   if (n > 0 && !states) return inval(c, "adjoint_sequence: need states");
   for (int64_t i = 0; i < n; ++i)
     if (!states[i]) return inval(c, "adjoint_sequence: states[i] is NULL");
   if (grad_force && !c->has_force_field) return inval(c, "adjoint_sequence: grad_force needs a bound force field");
+  // Pairs of steps run as one two-step adjoint launch; an odd one alone.
   void* mu[2] = {mu_a, mu_b};
-  for (int64_t i = n - 1, k = 0; i >= 0; --i, k ^= 1) {
-    lbm_status s = dev_err(c, lbm::launch_adjoint_step(c->args, states[i], mu[k], mu[k ^ 1], grad_force, c->stream),
-                           "adjoint step kernel");
+  int k = 0;
+  int64_t i = n - 1;
+  for (; i >= 1; i -= 2, k ^= 1) {
+    lbm_status s = dev_err(c, lbm::launch_adjoint_step2(c->args, states[i], states[i - 1], mu[k], mu[k ^ 1],
+                                                        grad_force, c->stream),
+                           "two-step adjoint kernel");
     if (s != LBM_OK) return s;
   }
+  if (i == 0) {
+    lbm_status s = dev_err(c, lbm::launch_adjoint_step(c->args, states[0], mu[k], mu[k ^ 1], grad_force, c->stream),
+                           "adjoint step kernel");
+    if (s != LBM_OK) return s;
+    k ^= 1;
+  }
+  *result_in_b = k;
   return LBM_OK;
 }
 

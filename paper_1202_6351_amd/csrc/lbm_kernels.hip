@@ -383,44 +383,22 @@ __device__ __forceinline__ void force_at(const KArgs<R>& a, int gx, int gy, R& F
   }
 }
 
-// Stores of one node's nine stored values (non-temporal; buffer path when
-// the lattice is below 4 GiB).
-template <typename S>
-__device__ __forceinline__ void store_node(const Geom& g, S* __restrict__ dst, int gx, int gy, const S o[9]) {
-  if (g.fast) {
-    const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
-    const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], o[k]);
-  } else {
-    const int64_t c = (int64_t)gy * g.pitch + gx;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
-  }
-}
-
 // Step n for one window cell from its nine pulled populations d, rounded and
-// kept in LDS (and returned in o).
+// kept in LDS.
 template <typename S, int FM, bool SR, int EH, int EW>
 __device__ __forceinline__ void collide_into_window(const KArgs<typename Codec<S>::R>& a,
                                                     const Rates<typename Codec<S>::R>& rt, int gx, int gy,
                                                     const typename Codec<S>::R d[9], uint32_t key,
-                                                    S (&mid)[9][EH][EW], int cx, int cy, S o[9]) {
+                                                    S (&mid)[9][EH][EW], int cx, int cy) {
   using R = typename Codec<S>::R;
   R Fx, Fy;
   force_at<FM>(a, gx, gy, Fx, Fy);
   R out[9];
   collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+  S o[9];
   round_out<S, SR>(out, (uint32_t)(gy * a.g.nx + gx), key, o);
 #pragma unroll
   for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[k];
-}
-
-// Window cell (cx, cy) of a window with an H-node ring around the 64 x TY
-// tile at (x0, y0): is it a node of the tile inside the domain?
-template <int H, int TY>
-__device__ __forceinline__ bool tile_cell(const Geom& g, int x0, int y0, int cx, int cy) {
-  return cx >= H && cx < H + 64 && cy >= H && cy < H + TY && x0 + cx - H < g.nx && y0 + cy - H < g.ny;
 }
 
 // Pull of window cell (gx, gy) for the first stage: from HBM, through the
@@ -456,21 +434,18 @@ __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>
     if (!window_node(a.g, wx0 + cx, wy0 + cy, gx, gy)) continue;
     R d[9];
     pull_hbm<S>(a, rs, src, fast, gx, gy, d);
-    S o[9];
-    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx, gy, d, key, mid, cx, cy, o);
+    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx, gy, d, key, mid, cx, cy);
   }
 }
 
 // The same with every load of the thread's cells issued before the first
 // collision, so that HBM latency is paid once per stage rather than once per
-// cell.  KEEP: the tile's own cells (the 64 x TY tile inside an H-node ring)
-// are also stored to `keep`, the state after this step.
-template <typename S, int FM, bool SR, int EH, int EW, int NT, bool KEEP = false, int H = 0, int TY = 0>
+// cell.
+template <typename S, int FM, bool SR, int EH, int EW, int NT>
 __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Codec<S>::R>& a,
                                                         const Rates<typename Codec<S>::R>& rt,
                                                         const S* __restrict__ src, int wx0, int wy0, bool fast,
-                                                        uint32_t key, S (&mid)[9][EH][EW],
-                                                        S* __restrict__ keep = nullptr) {
+                                                        uint32_t key, S (&mid)[9][EH][EW]) {
   using R = typename Codec<S>::R;
   constexpr int NPT = (EW * EH + NT - 1) / NT;
   const __amdgpu_buffer_rsrc_t rs = rsrc(src, a.g.lattice_bytes);
@@ -486,10 +461,7 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int i = (int)threadIdx.x + NT * j;
-    if (!live[j]) continue;
-    S o[9];
-    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW, o);
-    if (KEEP && tile_cell<H, TY>(a.g, wx0 + H, wy0 + H, i % EW, i / EW)) store_node<S>(a.g, keep, gx[j], gy[j], o);
+    if (live[j]) collide_into_window<S, FM, SR, EH, EW>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW);
   }
 }
 
@@ -497,13 +469,11 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 // outside the tile (the window has an H-node ring).  Every thread pulls and
 // collides its cells into registers; after a barrier it writes them back.
 // WALLS = false: the window lies inside the domain and no cell's link
-// crosses a wall.  KEEP: the tile's own cells (tile height TY) are also
-// stored to `keep`, the state after this step.
-template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool KEEP = false,
-          int TY = 0>
+// crosses a wall.
+template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT>
 __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
-                                             uint32_t key, S (&mid)[9][EH][EW], S* __restrict__ keep = nullptr) {
+                                             uint32_t key, S (&mid)[9][EH][EW]) {
   using R = typename Codec<S>::R;
   constexpr int RW = EW - 2 * (H - RING), RH = EH - 2 * (H - RING), NPT = (RW * RH + NT - 1) / NT;
   const Geom& g = a.g;
@@ -532,7 +502,6 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
     const int cx = H - RING + i % RW, cy = H - RING + i / RW;
 #pragma unroll
     for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[j][k];
-    if (KEEP && tile_cell<H, TY>(g, wx0 + H, wy0 + H, cx, cy)) store_node<S>(g, keep, wx0 + cx, wy0 + cy, o[j]);
   }
   __syncthreads();
 }
@@ -609,30 +578,25 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
 // tile plus a one-node ring in place in LDS; step n+2 on the tile to HBM.
 // HBM traffic per update is a third of a single step's; the rings cost
 // (68 (TY+4) + 66 (TY+2) + 64 TY) / (3 * 64 TY) - 1 = 21 % extra collisions
-// at TY = 12 (FP32: 39 KB of LDS, four workgroups per CU), 24 % at TY = 10
-// with 512 threads (FP64 above 2^20 nodes: 68.5 KB, two workgroups per CU)
-// and 56 % at TY = 4 (smaller FP64 lattices: 39 KB).
-//
-// KEEP: the states after the first and the second step are also stored, to
-// keep_a and keep_b (a segment recompute that keeps every state).
-template <typename S, int FM, bool SR, int TY, int NT, bool KEEP>
+// at TY = 12 (FP32: 39 KB of LDS, four workgroups per CU) and 56 % at TY = 4
+// (FP64: 39 KB).
+template <typename S, int FM, bool SR, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
-                                              S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
-                                              uint32_t key_c, S* __restrict__ keep_a, S* __restrict__ keep_b) {
+                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
+                                               uint32_t key_c) {
   constexpr int H = 2, EW = 64 + 2 * H, EH = TY + 2 * H;
   __shared__ S mid[9][EH][EW];
   const auto rt = rates(a);
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, KEEP, H, TY>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid,
-                                                                keep_a);
+  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
   if (interior) {  // workgroup-uniform: every thread meets the same barriers
-    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT, KEEP, TY>(a, rt, x0 - H, y0 - H, key_b, mid, keep_b);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
     stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
   } else {
-    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT, KEEP, TY>(a, rt, x0 - H, y0 - H, key_b, mid, keep_b);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
     stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
   }
 }
@@ -816,6 +780,94 @@ __global__ __launch_bounds__(256) void k_adjoint_step(KArgs<typename Codec<S>::R
   }
 }
 
+// Two adjoint steps per launch, newest first: the cotangent mu_in of state
+// n+1 goes back through step n (state n in prev_a) and then step n-1 (state
+// n-1 in prev_b) to the cotangent mu_out of state n-1.  A workgroup owns a
+// 64 x TY tile.  Stage 1 runs the adjoint of step n on the tile and a one-node
+// ring and scatters its reverse-streamed result into an LDS window (the
+// cotangent of state n, which each window position receives from exactly one
+// cell).  Stage 2 runs the adjoint of step n-1 on the tile from that window
+// and scatters to mu_out.  grad_force receives (g + aF_n) + aF_(n-1): the
+// same sums in the same order as two single adjoint steps, so the result is
+// bit-for-bit theirs.  HBM per node and two steps: mu in and out, both
+// states, force and gradient once -- 168 B (FP32) against 264.
+template <typename S, int TY>
+__global__ __launch_bounds__(256) void k_adjoint_step2(KArgs<typename Codec<S>::R> a, const S* __restrict__ prev_a,
+                                                       const S* __restrict__ prev_b,
+                                                       const typename Codec<S>::R* __restrict__ mu_in,
+                                                       typename Codec<S>::R* __restrict__ mu_out,
+                                                       typename Codec<S>::R* __restrict__ grad_force) {
+  using R = typename Codec<S>::R;
+  constexpr int H = 2, EW = 64 + 2 * H, EH = TY + 2 * H;
+  __shared__ R mid[9][EH][EW];      // cotangent of state n on the window
+  __shared__ R aF1[2][TY][64];      // stage 1 force cotangents of the tile
+  const Geom& g = a.g;
+  const Rates<R> r = rates(a);
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int x0 = (tile % g.t2_tiles_x) * 64, y0 = (tile / g.t2_tiles_x) * TY;
+  const int wx0 = x0 - H, wy0 = y0 - H;
+  // ---- stage 1: adjoint of step n on the tile and a one-node ring
+  constexpr int RW = EW - 2, RH = EH - 2;
+  for (int i = (int)threadIdx.x; i < RW * RH; i += 256) {
+    const int cx = 1 + i % RW, cy = 1 + i / RW;
+    int gx, gy;
+    if (!window_node(g, wx0 + cx, wy0 + cy, gx, gy)) continue;
+    R d[9];
+    gather<S, R>(g, a.wadd, prev_a, gx, gy, d);
+    R Fx, Fy;
+    node_force(a, gx, gy, Fx, Fy);
+    R out[9];
+    NodeFwd<R> st;
+    collide(r, Fx, Fy, d, out, st);
+    const int64_t c = (int64_t)gy * g.pitch + gx;
+    R mu[9], nu[9], ax = R(0), ay = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * g.plane + c];
+    collide_T(r, st, mu, nu, ax, ay);
+    const Edges e = edges(g, gx, gy);
+#define LBM_SCATTER_WIN(A)                                                        \
+    {                                                                             \
+      constexpr int sx = EX[A], sy = EY[A];                                       \
+      const bool hx = (sx == 1 && e.wxl) || (sx == -1 && e.wxh);                  \
+      const bool hy = (sy == 1 && e.wyl) || (sy == -1 && e.wyh);                  \
+      if (hx || hy) mid[OPP[A]][cy][cx] = nu[A];                                  \
+      else mid[A][cy - sy][cx - sx] = nu[A];                                      \
+    }
+    LBM_SCATTER_WIN(0) LBM_SCATTER_WIN(1) LBM_SCATTER_WIN(2) LBM_SCATTER_WIN(3) LBM_SCATTER_WIN(4)
+    LBM_SCATTER_WIN(5) LBM_SCATTER_WIN(6) LBM_SCATTER_WIN(7) LBM_SCATTER_WIN(8)
+#undef LBM_SCATTER_WIN
+    if (cx >= H && cx < H + 64 && cy >= H && cy < H + TY) {
+      aF1[0][cy - H][cx - H] = ax;
+      aF1[1][cy - H][cx - H] = ay;
+    }
+  }
+  __syncthreads();
+  // ---- stage 2: adjoint of step n-1 on the tile
+  const int lx = (int)threadIdx.x & 63;
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += 4) {
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= g.nx || gy >= g.ny) continue;
+    R d[9];
+    gather<S, R>(g, a.wadd, prev_b, gx, gy, d);
+    R Fx, Fy;
+    node_force(a, gx, gy, Fx, Fy);
+    R out[9];
+    NodeFwd<R> st;
+    collide(r, Fx, Fy, d, out, st);
+    R mu[9], nu[9], ax = R(0), ay = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mu[k] = mid[k][ly + H][lx + H];
+    collide_T(r, st, mu, nu, ax, ay);
+    scatter<R, R>(g, a.wadd, mu_out, gx, gy, nu, false);
+    if (grad_force) {
+      const int64_t cf = (int64_t)gy * g.nx + gx;
+      grad_force[cf] = (grad_force[cf] + aF1[0][ly][lx]) + ax;
+      const int64_t cg = (int64_t)g.nx * g.ny + cf;
+      grad_force[cg] = (grad_force[cg] + aF1[1][ly][lx]) + ay;
+    }
+  }
+}
+
 // Adjoint of the macroscopic map rho, u at lattice lat.
 template <typename S>
 __global__ __launch_bounds__(256) void k_adjoint_macro(KArgs<typename Codec<S>::R> a, const S* __restrict__ lat,
@@ -955,47 +1007,33 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
   }
 }
 
-template <typename S, bool SR, int TY, int NT, bool KEEP>
-static hipError_t launch_step3_keep(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                                    uint32_t kb, uint32_t kc, void* keep_a, void* keep_b, hipStream_t st) {
+template <typename S, bool SR, int TY, int NT>
+static hipError_t launch_step3_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                  uint32_t kb, uint32_t kc, hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(k.g.t3_tiles_x * k.g.t3_tiles_y));
   if (k.g.t3_ty != TY || k.g.t3_threads != NT) return hipErrorInvalidValue;
-  S* const a = (S*)keep_a;
-  S* const b = (S*)keep_b;
   if (fm == 0)
-    hipLaunchKernelGGL((k_step3<S, 0, SR, TY, NT, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
-                       kc, a, b);
+    hipLaunchKernelGGL((k_step3<S, 0, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
   else if (fm == 1)
-    hipLaunchKernelGGL((k_step3<S, 1, SR, TY, NT, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
-                       kc, a, b);
+    hipLaunchKernelGGL((k_step3<S, 1, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
   else
-    hipLaunchKernelGGL((k_step3<S, 2, SR, TY, NT, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
-                       kc, a, b);
+    hipLaunchKernelGGL((k_step3<S, 2, SR, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
   return hipGetLastError();
 }
 
-template <typename S, bool SR, int TY, int NT>
-static hipError_t launch_step3_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                                  uint32_t kb, uint32_t kc, void* keep_a, void* keep_b, hipStream_t st) {
-  if ((keep_a == nullptr) != (keep_b == nullptr)) return hipErrorInvalidValue;
-  return keep_a ? launch_step3_keep<S, SR, TY, NT, true>(k, src, dst, ka, kb, kc, keep_a, keep_b, st)
-                : launch_step3_keep<S, SR, TY, NT, false>(k, src, dst, ka, kb, kc, nullptr, nullptr, st);
-}
-
 hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
-                        uint32_t key_c, void* keep_a, void* keep_b, hipStream_t st) {
+                        uint32_t key_c, hipStream_t st) {
   // FP64 and FP32 only: the 16-bit modes run two steps per launch.
   switch (a.storage) {
     case 0:
       return a.d.g.t3_threads == kStep3ThreadsF64Large
-                 ? launch_step3_fm<double, false, kStep3TyF64Large, kStep3ThreadsF64Large>(
-                       a.d, src, dst, key_a, key_b, key_c, keep_a, keep_b, st)
-                 : launch_step3_fm<double, false, kStep3TyF64, kStep3ThreadsF64>(a.d, src, dst, key_a, key_b, key_c,
-                                                                                keep_a, keep_b, st);
+                 ? launch_step3_fm<double, false, kStep3TyF64Large, kStep3ThreadsF64Large>(a.d, src, dst, key_a,
+                                                                                          key_b, key_c, st)
+                 : launch_step3_fm<double, false, kStep3TyF64, kStep3ThreadsF64>(a.d, src, dst, key_a, key_b,
+                                                                                key_c, st);
     case 1:
-      return launch_step3_fm<float, false, kStep3TyF32, kStep3ThreadsF32>(a.f, src, dst, key_a, key_b, key_c,
-                                                                          keep_a, keep_b, st);
+      return launch_step3_fm<float, false, kStep3TyF32, kStep3ThreadsF32>(a.f, src, dst, key_a, key_b, key_c, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1057,6 +1095,29 @@ hipError_t launch_diag(const KArgsAny& a, const void* src, double* partial, int 
                        base_mass, out);
     return hipGetLastError();
   })
+}
+
+hipError_t launch_adjoint_step2(const KArgsAny& a, const void* prev_a, const void* prev_b, const void* mu_in,
+                                void* mu_out, void* grad_force, hipStream_t st) {
+  const Geom& g = a.g();
+  switch (a.storage) {
+    case 0: {
+      constexpr int TY = kAdjoint2TyF64;
+      const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
+      hipLaunchKernelGGL((k_adjoint_step2<double, TY>), grid, dim3(256), 0, st, a.d, (const double*)prev_a,
+                         (const double*)prev_b, (const double*)mu_in, (double*)mu_out, (double*)grad_force);
+      return hipGetLastError();
+    }
+    case 1: {
+      constexpr int TY = kAdjoint2TyF32;
+      const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
+      hipLaunchKernelGGL((k_adjoint_step2<float, TY>), grid, dim3(256), 0, st, a.f, (const float*)prev_a,
+                         (const float*)prev_b, (const float*)mu_in, (float*)mu_out, (float*)grad_force);
+      return hipGetLastError();
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_adjoint_step(const KArgsAny& a, const void* prev, const void* mu_in, void* mu_out,

@@ -37,6 +37,9 @@ constexpr int kStep3TyF64 = 4, kStep3ThreadsF64 = 256;
 constexpr int kStep3TyF64Large = 10, kStep3ThreadsF64Large = 512;
 constexpr int64_t kStep3LargeMinNodes = 1 << 20;
 
+// Two-step adjoint tile heights (64 x TY tiles, 256 threads).
+constexpr int kAdjoint2TyF32 = 8, kAdjoint2TyF64 = 4;
+
 // Kernel arguments in the compute real R.
 template <typename R>
 struct KArgs {
@@ -73,10 +76,9 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
                         hipStream_t st);
 // Three steps in one launch (FP64 and FP32 storage): src (state n) -> dst
 // (state n+3), keys of steps n, n+1, n+2.  Same result as three launch_step
-// calls.  keep_a, keep_b: both NULL, or buffers that also receive states
-// n+1 and n+2.
+// calls.
 hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
-                        uint32_t key_c, void* keep_a, void* keep_b, hipStream_t st);
+                        uint32_t key_c, hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);
@@ -87,6 +89,11 @@ hipError_t launch_diag(const KArgsAny& a, const void* src, double* partial, int 
                        double* out, hipStream_t st);
 hipError_t launch_adjoint_step(const KArgsAny& a, const void* prev, const void* mu_in, void* mu_out,
                                void* grad_force, hipStream_t st);
+// Two adjoint steps in one launch: mu_in (cotangent of state n+1) back
+// through step n (state n in prev_a) and step n-1 (state n-1 in prev_b) to
+// mu_out.  Same result as two launch_adjoint_step calls.
+hipError_t launch_adjoint_step2(const KArgsAny& a, const void* prev_a, const void* prev_b, const void* mu_in,
+                                void* mu_out, void* grad_force, hipStream_t st);
 hipError_t launch_adjoint_macro(const KArgsAny& a, const void* lat, const void* g_rho, const void* g_ux,
                                 const void* g_uy, void* mu_out, void* grad_force, hipStream_t st);
 hipError_t launch_adjoint_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy,

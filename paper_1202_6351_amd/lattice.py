@@ -232,9 +232,10 @@ class Lattice:
         the state after the last one).  Returns the buffer, mu_a or mu_b,
         that holds the cotangent of states[0]."""
         arr = (ctypes.c_void_p * len(states))(*[t.data_ptr() for t in states])
+        in_b = ctypes.c_int(0)
         self._check(_lib.lib().lbm_adjoint_sequence(self._ctx, arr, len(states), _ptr(mu_a), _ptr(mu_b),
-                                                    _ptr(grad_force)))
-        return mu_a if len(states) % 2 == 0 else mu_b
+                                                    _ptr(grad_force), ctypes.byref(in_b)))
+        return mu_b if in_b.value else mu_a
 
     def adjoint_macroscopic(self, lat, g_rho, g_ux, g_uy, mu_out, grad_force=None):
         self._check(_lib.lib().lbm_adjoint_macroscopic(self._ctx, _ptr(lat), _ptr(g_rho), _ptr(g_ux),
