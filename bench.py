@@ -4,7 +4,8 @@
 
 Headline (`value`): MLUPS of the plain FP32 step on the lid-driven cavity
 4096 x 4096 (Re 1000, lid 0.1, tau 1.7288; seeded density noise 1e-6), with
-the lattices resident in HBM: W untimed steps, then exactly K steps timed with
+the lattices resident in HBM: W untimed steps, then exactly K steps (default
+100 000, the study's step count at its largest grid) timed with
 HIP events on the library's stream (lbm_step fuses three steps per launch in
 FP32 and FP64, two in FP16/BF16).  One JSON line on stdout, also carrying:
   roofline      the dominant kernel (the three-step FP32 launch) against
@@ -18,6 +19,8 @@ FP32 and FP64, two in FP16/BF16).  One JSON line on stdout, also carrying:
                 update), so frac can exceed 1; the bytes actually moved and
                 their rate are reported beside it;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cavity;
+  sizes         MLUPS of the same cavity at 1024^2 and 2048^2 (Re 1000) and
+                at 4096^2, Re 5000 (2100 steps each);
   forms         FP16/BF16 deviation storage, round-to-nearest and
                 stochastic rounding, on Taylor-Green 8192 x 8192 (MLUPS,
                 roofline at 36 B per node and launch) with their velocity and
@@ -94,10 +97,10 @@ def timed_steps(lat, steps, warmup, group):
     return e0.elapsed_time(e2) / 1e3, e0.elapsed_time(e1) / 1e3, whole // group
 
 
-def cavity_lattice(n, storage):
+def cavity_lattice(n, storage, re=1000.0):
     import workloads as W
     from paper_1202_6351_amd import Lattice, Params
-    tau = W.cavity_tau(n, 0.1, 1000.0)
+    tau = W.cavity_tau(n, 0.1, re)
     p = Params(n, n, tau=tau, bc=("wall",) * 4, wall_u=(0, 0, 0, 0.1), storage=storage)
     lat = Lattice(p, device="cuda:0")
     lat.init_equilibrium(*W.at_rest(n, n, density_noise=1e-6, seed=2))
@@ -208,7 +211,7 @@ def copy_calibration(nbytes=1 << 30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2100)
+    ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
     ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64"], default=None,
@@ -277,12 +280,22 @@ def main():
     del lat
     torch.cuda.empty_cache()
     if args.only is None and not args.no_forms:
+        # the other grids and Reynolds number of the same cavity throughput study
+        sizes = {}
+        for ns, re in ((1024, 1000.0), (2048, 1000.0), (4096, 5000.0)):
+            ls, _ = cavity_lattice(ns, "fp32", re)
+            dts, _, _ = timed_steps(ls, 2100, 300, grp)
+            sizes[f"cavity_{ns}x{ns}_re{int(re)}_fp32"] = round(ns * ns * 2100 / dts / 1e6, 1)
+            del ls
+            torch.cuda.empty_cache()
+        line["sizes"] = sizes
+    if args.only is None and not args.no_forms:
         forms = {}
         for storage in ("fp16", "bf16"):
             for rounding in ("nearest", "stochastic"):
                 l16 = taylor_green_lattice(8192, storage, rounding=rounding)
                 g16 = UPDATES_PER_LAUNCH[storage]
-                steps16 = max(10, args.steps // 4)
+                steps16 = max(10, min(args.steps // 4, 2000))
                 steps16 -= steps16 % g16
                 dt16, _, launches16 = timed_steps(l16, steps16, max(2, args.warmup // 4), g16)
                 m16 = 8192 * 8192 * steps16 / dt16 / 1e6
