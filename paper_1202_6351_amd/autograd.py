@@ -92,10 +92,13 @@ class Rollout(torch.autograd.Function):
         free = [None, None]
 
         def recompute(s, b):
-            if free[b] is not None:
-                side.wait_event(free[b])  # the adjoint that read this set is done
-            rec.step_sequence(snaps[s], sets[b][:max(seg_len[s] - 1, 0)])
-            ready[b].record(side)
+            # issued with `side` current, so the call orders itself by these
+            # events only and does not make the main stream wait for it
+            with torch.cuda.stream(side):
+                if free[b] is not None:
+                    side.wait_event(free[b])  # the adjoint that read this set is done
+                rec.step_sequence(snaps[s], sets[b][:max(seg_len[s] - 1, 0)])
+                ready[b].record(side)
 
         recompute(nseg - 1, 0)
         for k, s in enumerate(range(nseg - 1, -1, -1)):

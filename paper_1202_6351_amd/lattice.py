@@ -140,6 +140,20 @@ class Lattice:
         for t in tensors:
             t.record_stream(self.stream)
 
+    def _after_caller(self):
+        # Inputs are produced on the caller's current stream: the library's
+        # stream (if another one) waits for them.
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _before_caller(self):
+        # Outputs are read on the caller's current stream: it (if another
+        # one) waits for the library's work.
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def _lattice_like(self, t: torch.Tensor, what: str):
         if not (t.is_cuda and t.is_contiguous() and t.numel() * t.element_size() >= self.nbytes):
             raise ValueError(f"{what}: need a contiguous device buffer of {self.nbytes} bytes")
@@ -165,19 +179,23 @@ class Lattice:
     def init_equilibrium(self, rho, ux, uy):
         shp = (self.params.ny, self.params.nx)
         r, vx, vy = (self._field(a, shp, torch.float64) for a in (rho, ux, uy))
+        self._after_caller()
         self._check(_lib.lib().lbm_init_equilibrium(self._ctx, _ptr(r), _ptr(vx), _ptr(vy)))
         self._hold(r, vx, vy)
         return self
 
     def set_populations(self, f):
         t = self._field(f, (9, self.params.ny, self.params.nx), torch.float64)
+        self._after_caller()
         self._check(_lib.lib().lbm_set_populations(self._ctx, _ptr(t)))
         self._hold(t)
         return self
 
     def populations(self) -> torch.Tensor:
         out = torch.empty((9, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+        self._after_caller()
         self._check(_lib.lib().lbm_get_populations(self._ctx, _ptr(out)))
+        self._before_caller()
         return out
 
     def step(self, n: int = 1):
@@ -187,7 +205,9 @@ class Lattice:
     def step_between(self, src: torch.Tensor, dst: torch.Tensor):
         self._lattice_like(src, "src")
         self._lattice_like(dst, "dst")
+        self._after_caller()
         self._check(_lib.lib().lbm_step_between(self._ctx, _ptr(src), _ptr(dst)))
+        self._before_caller()
 
     def step_sequence(self, src: torch.Tensor, states: Sequence[torch.Tensor]):
         """states[0] = step(src), states[i] = step(states[i-1]): a segment
@@ -196,16 +216,21 @@ class Lattice:
         for t in states:
             self._lattice_like(t, "states[i]")
         arr = (ctypes.c_void_p * len(states))(*[t.data_ptr() for t in states])
+        self._after_caller()
         self._check(_lib.lib().lbm_step_sequence(self._ctx, _ptr(src), arr, len(states)))
+        self._before_caller()
 
     def snapshot(self, dst: Optional[torch.Tensor] = None) -> torch.Tensor:
         dst = self.new_lattice() if dst is None else dst
         self._lattice_like(dst, "dst")
+        self._after_caller()
         self._check(_lib.lib().lbm_snapshot(self._ctx, _ptr(dst)))
+        self._before_caller()
         return dst
 
     def restore(self, src: torch.Tensor, t: int = 0):
         self._lattice_like(src, "src")
+        self._after_caller()
         self._check(_lib.lib().lbm_restore(self._ctx, _ptr(src), int(t)))
 
     def macroscopic(self, strain: bool = True) -> dict:
@@ -213,7 +238,9 @@ class Lattice:
         names = ["rho", "ux", "uy"] + (["sxx", "syy", "sxy"] if strain else [])
         out = {k: torch.empty(shp, dtype=torch.float64, device=self.device) for k in names}
         ptrs = [_ptr(out.get(k)) for k in ("rho", "ux", "uy", "sxx", "syy", "sxy")]
+        self._after_caller()
         self._check(_lib.lib().lbm_macroscopic(self._ctx, *ptrs))
+        self._before_caller()
         return out
 
     def diagnostics(self) -> np.ndarray:
@@ -224,8 +251,10 @@ class Lattice:
 
     # ------------------------------------------------------------- adjoint
     def adjoint_step(self, lat_prev, mu_in, mu_out, grad_force=None):
+        self._after_caller()
         self._check(_lib.lib().lbm_adjoint_step(self._ctx, _ptr(lat_prev), _ptr(mu_in), _ptr(mu_out),
                                                 _ptr(grad_force)))
+        self._before_caller()
 
     def adjoint_sequence(self, states: Sequence[torch.Tensor], mu_a, mu_b, grad_force=None):
         """Adjoint steps newest-first over states[0..n-1] (mu_a: cotangent of
@@ -233,14 +262,20 @@ class Lattice:
         that holds the cotangent of states[0]."""
         arr = (ctypes.c_void_p * len(states))(*[t.data_ptr() for t in states])
         in_b = ctypes.c_int(0)
+        self._after_caller()
         self._check(_lib.lib().lbm_adjoint_sequence(self._ctx, arr, len(states), _ptr(mu_a), _ptr(mu_b),
                                                     _ptr(grad_force), ctypes.byref(in_b)))
+        self._before_caller()
         return mu_b if in_b.value else mu_a
 
     def adjoint_macroscopic(self, lat, g_rho, g_ux, g_uy, mu_out, grad_force=None):
+        self._after_caller()
         self._check(_lib.lib().lbm_adjoint_macroscopic(self._ctx, _ptr(lat), _ptr(g_rho), _ptr(g_ux),
                                                        _ptr(g_uy), _ptr(mu_out), _ptr(grad_force)))
+        self._before_caller()
 
     def adjoint_init(self, rho, ux, uy, mu0, g_rho=None, g_ux=None, g_uy=None, grad_force=None):
+        self._after_caller()
         self._check(_lib.lib().lbm_adjoint_init(self._ctx, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(mu0),
                                                 _ptr(g_rho), _ptr(g_ux), _ptr(g_uy), _ptr(grad_force)))
+        self._before_caller()

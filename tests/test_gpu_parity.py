@@ -243,3 +243,21 @@ def test_multi_step_launch_large_shape(storage, bci, force):
         b.step(1)
     assert torch.equal(a.populations(), b.populations())
 
+
+
+def test_lattice_on_its_own_stream():
+    """A Lattice bound to a stream other than the caller's: its outputs are
+    ordered before the caller's stream reads them, and the caller's inputs
+    before the library reads them."""
+    from paper_1202_6351_amd import Lattice, Params
+    n = 256
+    p = Params(n, n, tau=0.7, bc=("wall",) * 4, wall_u=(0, 0, 0, 0.05), storage="fp32")
+    ref = Lattice(p, device="cuda:0").init_equilibrium(*W.at_rest(n, n, density_noise=1e-4, seed=1)).step(200)
+    side = torch.cuda.Stream()
+    lat = Lattice(p, device="cuda:0", stream=side)
+    rho, ux, uy = (torch.from_numpy(a).cuda() for a in W.at_rest(n, n, density_noise=1e-4, seed=1))
+    lat.init_equilibrium(rho, ux, uy).step(200)
+    m, mr = lat.macroscopic(), ref.macroscopic()
+    for k in mr:
+        assert torch.equal(m[k], mr[k]), k
+    assert torch.equal(lat.populations(), ref.populations())
