@@ -17,7 +17,9 @@ FP32 and FP64, two in FP16/BF16).  One JSON line on stdout, also carrying:
                 launches).  Fusing three steps moves only a third of those
                 bytes (the state read and written once per launch, 24 B per
                 update), so frac can exceed 1; the bytes actually moved and
-                their rate are reported beside it;
+                their rate are reported beside it, and so is the VALU issue
+                rate from the committed SQ_INSTS_VALU count against the
+                chip's 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cavity;
   sizes         MLUPS of the same cavity at 1024^2 and 2048^2 (Re 1000) and
                 at 4096^2, Re 5000 (2100 steps each);
@@ -56,6 +58,10 @@ METRIC = "MLUPS + % HBM peak, FP32 vs FP16-storage; fwd+adjoint MLUPS at fixed e
 STEP_SOURCES = ["paper_1202_6351_amd/csrc/lbm_kernels.hip", "paper_1202_6351_amd/csrc/cascade.h",
                 "paper_1202_6351_amd/csrc/lbm_launch.h", "paper_1202_6351_amd/csrc/lbm_api.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step3_fp32_cavity4096.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_step3_fp32_cavity4096.txt")
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed lane
+# instructions per second).
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def kernel_hash() -> str:
@@ -66,17 +72,27 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP32 step from the committed counter
-    summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _counter_value(path, key):
+    """A per-launch figure from a committed counter summary, if the counters
+    were taken on the current kernel source."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256:\s*(\w+)", txt)
-    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_val = re.search(key + r":\s*([0-9.eE+]+)", txt)
     if not (m_hash and m_val) or m_hash.group(1) != kernel_hash():
         return None
     return float(m_val.group(1))
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 step (FETCH_SIZE + WRITE_SIZE)."""
+    return _counter_value(TRAFFIC_FILE, "traffic_bytes_per_launch")
+
+
+def measured_valu():
+    """VALU wave instructions per launch of the FP32 step (SQ_INSTS_VALU)."""
+    return _counter_value(VALU_FILE, "valu_wave_instructions_per_launch")
 
 
 def timed_steps(lat, steps, warmup, group):
@@ -259,6 +275,7 @@ def main():
     achieved = moved * grp  # algorithmic: 72 B per cell update, grp updates per node
     d = lat.diagnostics()  # raises on a non-finite state
     traffic = measured_traffic() if n == 4096 else None
+    valu = measured_valu() if n == 4096 else None
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
@@ -275,8 +292,14 @@ def main():
                      "alg_bytes_per_update": BYTES_PER_NODE["fp32"],
                      "moved_bytes_per_update": BYTES_PER_NODE["fp32"] / grp,
                      "moved_gbs": round(moved, 1), "moved_frac": round(moved / HBM_PEAK_GBS, 4),
+                     "valu": None if valu is None else {
+                         "lane_instructions_per_update": round(valu * 64 / (grp * n * n), 1),
+                         "achieved_tops": round(valu * 64 / per_launch / 1e12, 2),
+                         "peak_tops": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                         "frac": round(valu * 64 / per_launch / VALU_PEAK_LANE_OPS, 4)},
                      "note": "three steps per launch: the state crosses HBM once per three updates, "
-                             "so the algorithmic rate exceeds the single-pass HBM roofline"},
+                             "so the algorithmic rate exceeds the single-pass HBM roofline; the launch "
+                             "is bound by VALU issue and HBM together (valu, moved_frac)"},
         "mass_drift_rel": float(f"{abs(d[0] / (n * n) - 1.0):.2e}"),
     }
     del lat
