@@ -29,7 +29,7 @@ FP32 and FP64, two in FP16/BF16).  One JSON line on stdout, also carrying:
                 bytes moved, 36 B per node per two-step launch) with their
                 velocity and
                 strain-rate error against the FP64 path on Taylor-Green
-                512 x 512 after 20k steps; forward + adjoint rollout MLUPS on
+                512 x 512 after 20k steps at tau 0.8 and 0.55; forward + adjoint rollout MLUPS on
                 512 x 512 FP32 (T = 2000, checkpoint every 100) with the FP32
                 gradient's relative error against the FP64 gradient.
 """
@@ -153,26 +153,26 @@ def cpu_baseline(n, tau, budget_s=15.0):
                       f"from the benchmark's initial state ({dt:.1f} s)"}
 
 
-def precision_errors(n=512, steps=20000):
+def precision_errors(n=512, steps=20000, tau=0.8):
     """Velocity and strain-rate relative error (Sec. III norm) of FP32, FP16
     and BF16 storage against the FP64 path, Taylor-Green n x n, U0 0.05,
-    tau 0.8, noise 1e-5."""
+    noise 1e-5, relaxation time tau."""
     import numpy as np
     import torch
     out = {}
-    ref = taylor_green_lattice(n, "fp64").step(steps).macroscopic()
+    ref = taylor_green_lattice(n, "fp64", tau=tau).step(steps).macroscopic()
     ref = {k: v.cpu().numpy() for k, v in ref.items()}
     den_u = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).sum()
     for storage, rounding in (("fp32", "nearest"), ("fp16", "nearest"), ("bf16", "nearest"),
                               ("fp16", "stochastic"), ("bf16", "stochastic")):
-        m = taylor_green_lattice(n, storage, rounding=rounding).step(steps).macroscopic()
+        m = taylor_green_lattice(n, storage, tau=tau, rounding=rounding).step(steps).macroscopic()
         m = {k: v.cpu().numpy() for k, v in m.items()}
         eu = np.sqrt((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2).sum() / den_u
         es = np.abs(m["sxx"] - ref["sxx"]).sum() / np.abs(ref["sxx"]).sum()
         key = storage if rounding == "nearest" else f"{storage}_sr"
         out[key] = {"u_rel_err": float(f"{eu:.3e}"), "sxx_rel_err": float(f"{es:.3e}")}
     torch.cuda.synchronize()
-    return {"workload": f"taylor_green_{n}x{n}_u0.05_tau0.8_{steps}steps", "reference": "fp64 GPU path",
+    return {"workload": f"taylor_green_{n}x{n}_u0.05_tau{tau}_{steps}steps", "reference": "fp64 GPU path",
             **out}
 
 
@@ -334,6 +334,7 @@ def main():
                 del l16
                 torch.cuda.empty_cache()
         forms["error_vs_fp64"] = precision_errors()
+        forms["error_vs_fp64_tau0.55"] = precision_errors(tau=0.55)
         forms["fwd_adjoint"] = adjoint_rollout()
         line["forms"] = forms
     if args.only is None and not args.no_cpu_baseline:
