@@ -52,6 +52,9 @@ def test_layout_pitch_and_bytes():
     (dict(bc=("periodic", "wall", "periodic", "periodic")), "periodic on one side"),
     (dict(wall_u=(0.0, 0.0, 0.1, 0.0)), "periodic side"),
     (dict(rho0=0.0), "rho0"),
+    (dict(storage="fp32", rounding="stochastic"), "stochastic rounding needs"),
+    (dict(fx=float("inf")), "body force"),
+    (dict(nx=65536, ny=16384, storage="fp32"), "exceeds 4 GiB"),  # plane of exactly 2^32 bytes
 ])
 def test_invalid_parameters_rejected(kw, msg):
     from paper_1202_6351_amd import _lib, lattice_layout
@@ -71,3 +74,11 @@ def test_create_rejects_null_and_misaligned_buffers():
     st = lib.lbm_create(ctypes.byref(cp), ctypes.c_void_p(0x1000 + 8), ctypes.c_void_p(0x20000),
                         None, None, ctypes.byref(ctx))
     assert st == _lib.LBM_EINVAL and b"aligned" in lib.lbm_last_error(None)
+
+
+def test_largest_plane_accepted():
+    """A plane one row below the 4 GiB limit of the 32-bit plane offsets."""
+    from paper_1202_6351_amd import lattice_layout
+    pitch, nbytes = lattice_layout(_params(nx=65536, ny=16383, storage="fp32"))
+    assert pitch == 65536 and nbytes == 9 * 16383 * 65536 * 4
+
