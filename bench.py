@@ -64,6 +64,13 @@ VALU_FILE = os.path.join(ROOT, "profiles", "valu_step3_fp32_cavity4096.txt")
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def three_step_kernel(n: int) -> str:
+    """The kernel the library runs for an n x n FP32 lattice's three-step
+    launches: strips up to 6 Mi nodes, 64 x TY tiles above."""
+    name = "k_strip<float>" if n * n <= 6 * (1 << 20) else "k_step3<float>"
+    return f"{name} (three steps per launch)"
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for rel in STEP_SOURCES:
@@ -286,7 +293,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": "k_step3<float> (three steps per launch)",
+                     "kernel": three_step_kernel(n),
                      "launch_us": round(per_launch * 1e6, 2),
                      "updates_per_launch": grp,
                      "alg_bytes_per_update": BYTES_PER_NODE["fp32"],

@@ -4,7 +4,9 @@
 
 Compiles every source under csrc/ with hipcc, in-tree, so the library ships
 with the package directory.  Packed FP32 instructions are disabled
-(-packed-fp32-ops) for all device code.
+(-packed-fp32-ops) for all device code, and floating-point contraction is
+limited to single expressions (-ffp-contract=on): the fused multi-step
+kernels must round exactly as the single step does.
 """
 from __future__ import annotations
 
@@ -21,6 +23,9 @@ ARCH = "gfx950"
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds fused only where one source expression asks for it, so an
+    # inlined function rounds the same in every kernel
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,

@@ -57,9 +57,26 @@ constexpr int DIR[3][3] = {{7, 4, 8}, {3, 0, 1}, {6, 2, 5}};
 template <typename R>
 struct Rates {
   R w3, w4, w5, w6, w7, w8;        // relaxation rates omega_3..omega_8
-  R k3, k4, k5, k6, k7, k8;        // 1 - omega
+  R hw3, hw4, w5x2;                // omega_3 / 2, omega_4 / 2, 2 omega_5 (exact scalings)
   R rho0;                          // reference density of the deviations
 };
+
+template <typename R>
+LBM_HD Rates<R> make_rates(const R w[6], R rho0) {
+  Rates<R> r;
+  r.w3 = w[0]; r.w4 = w[1]; r.w5 = w[2]; r.w6 = w[3]; r.w7 = w[4]; r.w8 = w[5];
+  r.hw3 = R(0.5) * r.w3;
+  r.hw4 = R(0.5) * r.w4;
+  r.w5x2 = R(2) * r.w5;
+  r.rho0 = rho0;
+  return r;
+}
+
+// a * b + c rounded once.  Every fused multiply-add of the step's collision
+// is written out, so its rounding is fixed by the source and identical in
+// every kernel the collision is inlined into.
+LBM_HD float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+LBM_HD double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Intermediates of the forward pass that the reverse pass needs.
 template <typename R>
@@ -360,61 +377,91 @@ __device__ __forceinline__ float recip(float x) {
   return r * __builtin_fmaf(-x, r, 2.0f);
 }
 
-// Shift central -> raw for a column whose zeroth entry is 0.
-template <typename R>
-LBM_HD void ax_unc0(R u, R c1, R c2, R& m0, R& m1, R& m2) {
-  m0 = R(0);
-  m1 = c1;
-  m2 = c2 + R(2) * u * c1;
-}
-
-// The collision of the step kernel: the same function as collide(), written
-// out for Delta C_00 = 0 always and Delta C_10 = Delta C_01 = 0 without a
-// body force, so those zero terms cost no instructions.
+// The collision of the step kernels: the same function as collide(), in the
+// fewest operations.  Differences from collide()'s route, all exact in real
+// arithmetic: Delta C_00 = 0 and, without a body force, Delta C_10 =
+// Delta C_01 = 0, so those terms are dropped; without a body force the
+// first-order central moments of d are rho0 u, which stand in for the
+// products rho0 u_x, rho0 u_y of the attractors; the 2 Delta C_11, and
+// twice the outer rows of the y inverse, are carried so that the factors 1/2
+// and 1/4 of the inverse fold into the final multiply-adds.
 template <typename R, bool kForce>
 LBM_HD void collide_step(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9]) {
-  R M[3][3], X[3][3], C[3][3], D[3][3];
+  R M[3][3];
   raw_moments(d, M);
   const R drho = M[0][0];
   const R inv = recip(r.rho0 + drho);
-  const R ux = (kForce ? M[1][0] + R(0.5) * Fx : M[1][0]) * inv;
-  const R uy = (kForce ? M[0][1] + R(0.5) * Fy : M[0][1]) * inv;
-  central(ux, uy, M, X, C);
-  relax_delta(r, drho, ux, uy, Fx, Fy, C, D);
-  // back to raw moments: y shift per m, then x shift per n
-  R Y[3][3], Mo[3][3];
-  if (kForce) {
-    ax_unc0(uy, D[0][1], D[0][2], Y[0][0], Y[0][1], Y[0][2]);
-    ax_unc(uy, D[1][0], D[1][1], D[1][2], Y[1][0], Y[1][1], Y[1][2]);
-  } else {
-    Y[0][0] = R(0);
-    Y[0][1] = R(0);
-    Y[0][2] = D[0][2];
-    ax_unc0(uy, D[1][1], D[1][2], Y[1][0], Y[1][1], Y[1][2]);
-  }
-  ax_unc(uy, D[2][0], D[2][1], D[2][2], Y[2][0], Y[2][1], Y[2][2]);
-  ax_unc0(ux, Y[1][0], Y[2][0], Mo[0][0], Mo[1][0], Mo[2][0]);
-  if (kForce) {
-    ax_unc(ux, Y[0][1], Y[1][1], Y[2][1], Mo[0][1], Mo[1][1], Mo[2][1]);
-  } else {
-    ax_unc0(ux, Y[1][1], Y[2][1], Mo[0][1], Mo[1][1], Mo[2][1]);
-  }
-  ax_unc(ux, Y[0][2], Y[1][2], Y[2][2], Mo[0][2], Mo[1][2], Mo[2][2]);
-  // inverse transform (y then x) and add to d
-  R B[3][3];
-  B[0][0] = R(0.5) * (Mo[0][2] - Mo[0][1]);  // column m = 0 has Mo[0][0] = 0
-  B[1][0] = -Mo[0][2];
-  B[2][0] = R(0.5) * (Mo[0][2] + Mo[0][1]);
-  ax_inv(Mo[1][0], Mo[1][1], Mo[1][2], B[0][1], B[1][1], B[2][1]);
-  ax_inv(Mo[2][0], Mo[2][1], Mo[2][2], B[0][2], B[1][2], B[2][2]);
+  const R ux = (kForce ? fmad(R(0.5), Fx, M[1][0]) : M[1][0]) * inv;
+  const R uy = (kForce ? fmad(R(0.5), Fy, M[0][1]) : M[0][1]) * inv;
+  // Central moments of d about u: shift in x (X1, X2 per column n), then in y.
+  R X1[3], X2[3];
 #pragma unroll
-  for (int J = 0; J < 3; ++J) {
-    R pm, p0, pp;
-    ax_inv(B[J][0], B[J][1], B[J][2], pm, p0, pp);
-    out[DIR[J][0]] = d[DIR[J][0]] + pm;
-    out[DIR[J][1]] = d[DIR[J][1]] + p0;
-    out[DIR[J][2]] = d[DIR[J][2]] + pp;
+  for (int n = 0; n < 3; ++n) {
+    X1[n] = fmad(-ux, M[0][n], M[1][n]);
+    X2[n] = fmad(-ux, M[1][n] + X1[n], M[2][n]);
   }
+  const R C01 = fmad(-uy, M[0][0], M[0][1]);
+  const R C02 = fmad(-uy, M[0][1] + C01, M[0][2]);
+  const R C11 = fmad(-uy, X1[0], X1[1]);
+  const R C12 = fmad(-uy, X1[1] + C11, X1[2]);
+  const R C20 = X2[0];
+  const R C21 = fmad(-uy, X2[0], X2[1]);
+  const R C22 = fmad(-uy, X2[1] + C21, X2[2]);
+  const R r0ux = kForce ? r.rho0 * ux : X1[0];  // C_10 = rho0 u_x - F_x / 2
+  const R r0uy = kForce ? r.rho0 * uy : C01;
+  // Relaxation: Delta C = omega (E - C), E the attractors in deviation form.
+  const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+  const R q = ux2 + uy2, p = ux2 - uy2;
+  const R as = r.hw3 * fmad(-r.rho0, q, fmad(R(2.0 / 3.0), drho, -(C20 + C02)));
+  const R ad = r.hw4 * fmad(-r.rho0, p, -(C20 - C02));
+  const R D20 = as + ad, D02 = as - ad;
+  const R E11mC = fmad(-r.rho0, uxy, -C11);
+  const R D21 = r.w6 * fmad(r0uy, ux2 + R(1.0 / 3.0), -C21);
+  const R D12 = r.w7 * fmad(r0ux, uy2 + R(1.0 / 3.0), -C12);
+  const R D22 = r.w8 * fmad(-r.rho0, fmad(q, R(1.0 / 3.0), uxy * uxy), fmad(R(1.0 / 9.0), drho, -C22));
+  // Back to raw moments (shift by +u, y then x) and the inverse transform
+  // (y then x), added to d.  B0, B2: twice the rows e_y = -1, +1 of the y
+  // inverse; B1: the row e_y = 0.
+  R B0[3], B1[3], B2[3];
+  if constexpr (kForce) {
+    const R D11 = r.w5 * E11mC;
+    const R Y02 = fmad(uy + uy, Fy, D02);
+    const R Y11 = fmad(uy, Fx, D11);
+    const R Y12 = fmad(uy, D11 + Y11, D12);
+    const R Y21 = fmad(uy, D20, D21);
+    const R Y22 = fmad(uy, D21 + Y21, D22);
+    const R Mo20 = fmad(ux + ux, Fx, D20);
+    const R Mo11 = fmad(ux, Fy, Y11);
+    const R Mo21 = fmad(ux, Y11 + Mo11, Y21);
+    const R Mo12 = fmad(ux, Y02, Y12);
+    const R Mo22 = fmad(ux, Y12 + Mo12, Y22);
+    // columns m = 0 (Mo00 = 0, Mo01 = F_y, Mo02 = Y02), 1 (F_x, Mo11, Mo12), 2
+    B1[0] = -Y02;        B0[0] = Y02 - Fy;     B2[0] = Y02 + Fy;
+    B1[1] = Fx - Mo12;   B0[1] = Mo12 - Mo11;  B2[1] = Mo12 + Mo11;
+    B1[2] = Mo20 - Mo22; B0[2] = Mo22 - Mo21;  B2[2] = Mo22 + Mo21;
+  } else {
+    const R D11x2 = r.w5x2 * E11mC;
+    const R Y12 = fmad(uy, D11x2, D12);
+    const R Y21 = fmad(uy, D20, D21);
+    const R Y22 = fmad(uy, D21 + Y21, D22);
+    const R Mo21 = fmad(ux, D11x2, Y21);
+    const R Mo12 = fmad(ux, D02, Y12);
+    const R Mo22 = fmad(ux, Y12 + Mo12, Y22);
+    // columns m = 0 (0, 0, D02), 1 (0, D11, Mo12), 2 (D20, Mo21, Mo22)
+    B1[0] = -D02;        B0[0] = D02;                          B2[0] = D02;
+    B1[1] = -Mo12;       B0[1] = fmad(R(-0.5), D11x2, Mo12);  B2[1] = fmad(R(0.5), D11x2, Mo12);
+    B1[2] = D20 - Mo22;  B0[2] = Mo22 - Mo21;                  B2[2] = Mo22 + Mo21;
+  }
+  // x inverse per row: p0 = m0 - m2, p-+ = (m2 -+ m1) / 2.
+  out[DIR[1][1]] = d[DIR[1][1]] + (B1[0] - B1[2]);
+  out[DIR[1][0]] = fmad(R(0.5), B1[2] - B1[1], d[DIR[1][0]]);
+  out[DIR[1][2]] = fmad(R(0.5), B1[2] + B1[1], d[DIR[1][2]]);
+  out[DIR[0][1]] = fmad(R(0.5), B0[0] - B0[2], d[DIR[0][1]]);
+  out[DIR[0][0]] = fmad(R(0.25), B0[2] - B0[1], d[DIR[0][0]]);
+  out[DIR[0][2]] = fmad(R(0.25), B0[2] + B0[1], d[DIR[0][2]]);
+  out[DIR[2][1]] = fmad(R(0.5), B2[0] - B2[2], d[DIR[2][1]]);
+  out[DIR[2][0]] = fmad(R(0.25), B2[2] - B2[1], d[DIR[2][0]]);
+  out[DIR[2][2]] = fmad(R(0.25), B2[2] + B2[1], d[DIR[2][2]]);
 }
 
 }  // namespace lbm

@@ -24,6 +24,7 @@ struct lbm_ctx {
   double* diag_scratch;  // device: partial sums (diag_blocks * 4) + result (4)
   int diag_blocks;
   int64_t pitch, lattice_bytes;
+  bool strip3;        // three-step launches take the strip kernel (else 64 x TY tiles)
   char err[512];
 };
 
@@ -195,6 +196,24 @@ lbm_status lbm_lattice_layout(const lbm_params* p, int64_t* pitch, int64_t* byte
   return LBM_OK;
 }
 
+// Strip tiling of a fused launch of `steps` steps: strips of 64 - 2 (steps -
+// 1) columns, cut into segments so that all workgroups of the launch are
+// resident at once (one wave of workgroups, no tail), each segment a multiple
+// of `waves` rows and at least kStripMinLen.
+static lbm::StripTiling strip_tiling(int nx, int ny, int steps, int waves, int resident) {
+  lbm::StripTiling t;
+  const int tw = 64 - 2 * (steps - 1);
+  t.strips = (nx + tw - 1) / tw;
+  const int per = lbm::kStripRounds * resident / t.strips;
+  const int per_strip = per > 1 ? per : 1;
+  int len = (ny + per_strip - 1) / per_strip;
+  len = (len + waves - 1) / waves * waves;
+  if (len < lbm::kStripMinLen) len = lbm::kStripMinLen;
+  t.len = len;
+  t.segs = (ny + len - 1) / len;
+  return t;
+}
+
 lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* force_field,
                       void* stream, lbm_ctx** out) {
   if (!out) { set_err(g_create_err, "out is NULL"); return LBM_EINVAL; }
@@ -221,6 +240,11 @@ lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* f
   c->args.stochastic = p->rounding == LBM_ROUND_STOCHASTIC;
   if (p->storage == LBM_FP64) fill_args<double>(p, c->pitch, force_field, c->args.d);
   else fill_args<float>(p, c->pitch, force_field, c->args.f);
+  c->strip3 = p->storage == LBM_FP32 && (int64_t)p->nx * p->ny <= lbm::kStripMaxNodes;
+  if (c->strip3) {
+    const int resident = lbm::strip3_resident();
+    c->args.f.g.st3 = strip_tiling(p->nx, p->ny, 3, lbm::kStripWaves, resident > 0 ? resident : 1280);
+  }
   // Diagnostics: a fixed number of blocks (enough to fill 256 CUs), so the
   // reduction order does not depend on the grid size.
   c->diag_blocks = 1024;
@@ -292,9 +316,9 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   const int group = steps_per_launch(c->p.storage);
   int64_t left = n;
   for (; group == 3 && left >= 3; left -= 3) {
-    lbm_status s = dev_err(c, lbm::launch_step3(c->args, c->lat[c->cur], c->lat[c->cur ^ 1],
-                                                step_key(c->p, c->t), step_key(c->p, c->t + 1),
-                                                step_key(c->p, c->t + 2), c->stream),
+    const auto launch3 = c->strip3 ? lbm::launch_strip3 : lbm::launch_step3;
+    lbm_status s = dev_err(c, launch3(c->args, c->lat[c->cur], c->lat[c->cur ^ 1], step_key(c->p, c->t),
+                                      step_key(c->p, c->t + 1), step_key(c->p, c->t + 2), c->stream),
                            "three-step kernel");
     if (s != LBM_OK) return s;
     c->cur ^= 1;

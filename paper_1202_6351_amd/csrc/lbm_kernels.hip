@@ -17,12 +17,16 @@
 //
 // Launch shape of the single step: 256-thread blocks covering TX x (256/TX)
 // nodes, TX in {64, 128, 256} (a 64-wide wavefront spans one row segment).
-// The fused launches (k_step2, k_step3) give each workgroup a 64 x TY tile
-// and keep the intermediate steps of the tile and a recompute ring in LDS,
-// so the state crosses HBM once per two or three steps.  In every kernel the
-// 1-D block index is remapped so that each of the 8 XCDs (blocks are dealt
-// to XCDs round-robin) processes one contiguous band of tiles, keeping the
-// lines shared between horizontally and vertically adjacent tiles in one L2.
+// The fused launches keep intermediate steps in LDS, so the state crosses
+// HBM once per two or three steps.  k_step2 and k_step3 give each workgroup
+// a 64 x TY tile plus a recompute ring (two or three steps); k_strip gives it
+// a strip of 60 columns that it walks down row by row, one wavefront per row
+// and step, the intermediate rows in small LDS rings, so that only the strip's
+// sides are recomputed (three steps, FP32 lattices up to 6 Mi nodes, where
+// it leads).  In every kernel the 1-D block index is remapped so that each of
+// the 8 XCDs (blocks are dealt to XCDs round-robin) processes one contiguous
+// band of tiles, keeping the lines shared between horizontally and
+// vertically adjacent tiles in one L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -191,12 +195,7 @@ __device__ __forceinline__ void node_force(const KArgs<R>& a, int x, int y, R& F
 
 template <typename R>
 __device__ __forceinline__ Rates<R> rates(const KArgs<R>& a) {
-  Rates<R> r;
-  r.w3 = a.w[0]; r.w4 = a.w[1]; r.w5 = a.w[2]; r.w6 = a.w[3]; r.w7 = a.w[4]; r.w8 = a.w[5];
-  r.k3 = R(1) - r.w3; r.k4 = R(1) - r.w4; r.k5 = R(1) - r.w5;
-  r.k6 = R(1) - r.w6; r.k7 = R(1) - r.w7; r.k8 = R(1) - r.w8;
-  r.rho0 = a.rho0;
-  return r;
+  return make_rates<R>(a.w, a.rho0);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -218,9 +217,10 @@ template <> struct BufIO<float> {
   __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
   }
+  template <int CP = kNonTemporal>
   __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, (int)soff,
-                                          kNonTemporal);
+                                          CP);
   }
 };
 template <> struct BufIO<double> {
@@ -228,26 +228,29 @@ template <> struct BufIO<double> {
   __device__ static double load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0));
   }
+  template <int CP = kNonTemporal>
   __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, (int)soff, kNonTemporal);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, (int)soff, CP);
   }
 };
 template <> struct BufIO<_Float16> {
   __device__ static _Float16 load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0));
   }
+  template <int CP = kNonTemporal>
   __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, _Float16 v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, (int)soff,
-                                          kNonTemporal);
+                                          CP);
   }
 };
 template <> struct BufIO<__bf16> {
   __device__ static __bf16 load(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0));
   }
+  template <int CP = kNonTemporal>
   __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, __bf16 v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, (int)soff,
-                                          kNonTemporal);
+                                          CP);
   }
 };
 
@@ -599,6 +602,253 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
     stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
     stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
   }
+}
+
+// ------------------------------------------------------------ strip kernels
+// NS fused steps per launch, tiled in strips.  A workgroup of NW wavefronts
+// owns the TW = 64 - 2 (NS - 1) columns [x0, x0 + TW) of rows [ys, ye) and
+// walks down them, NW rows per iteration.  Each wavefront works on one window
+// row of 64 nodes per step; lane l holds window column x0 - (NS - 1) + l.  In
+// an iteration where the wavefront's step-0 row is r0, step s computes lanes
+// [s, 64 - s) of row r0 - s: step 0 pulls from HBM, step s > 0 from the LDS
+// ring holding step s - 1 (rows r - 1 .. r + 1), the last step stores to HBM.
+// The halo is recomputed only at the strip's sides (2 (NS - 1) of 64 lanes)
+// and at the segment's two ends, never between consecutive rows.
+//
+// Ring sizes: with a barrier after every step but the last, at most NW + 2
+// rows of an intermediate step are alive at once (the NW rows just computed
+// and the two below them).  With NS = 2 the next iteration's step 0 overlaps
+// the last step of this one, so its ring needs 2 NW + 2 rows.
+template <int RING>
+__device__ __forceinline__ int ring_slot(int r) {
+  return (r + 8 * RING) % RING;  // r >= -8 for every row a segment touches
+}
+
+// The nine populations streaming into node (gx, gy) held at lane l of window
+// row r, pulled from the ring of the previous step; sm, s0, sp are the slots
+// of rows r - 1, r, r + 1.
+template <bool WALLS, typename S, typename R, int RING>
+__device__ __forceinline__ void pull_ring(const KArgs<R>& a, int gx, int gy, const S (&rg)[9][RING][64], int l,
+                                          int sm, int s0, int sp, R d[9]) {
+  const int row[3] = {sp, s0, sm};  // indexed by e_y + 1: the source row is r - e_y
+  if constexpr (!WALLS) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(rg[k][row[EY[k] + 1]][l - EX[k]]);
+    return;
+  }
+  const Edges e = edges(a.g, gx, gy);
+#define LBM_PULL_RING(A)                                                                       \
+  {                                                                                            \
+    constexpr int ax = EX[A], ay = EY[A];                                                      \
+    const bool hx = (ax == 1 && e.wxl) || (ax == -1 && e.wxh);                                 \
+    const bool hy = (ay == 1 && e.wyl) || (ay == -1 && e.wyh);                                 \
+    const R add = hx == hy ? R(0)                                                              \
+                           : (hx ? a.wadd[(ax == 1 ? 0 : 1) * 9 + A]                           \
+                                 : a.wadd[(ay == 1 ? 2 : 3) * 9 + A]);                         \
+    d[A] = (hx || hy) ? Codec<S>::load(rg[OPP[A]][s0][l]) + add                                \
+                      : Codec<S>::load(rg[A][row[ay + 1]][l - ax]);                            \
+  }
+  LBM_PULL_RING(0) LBM_PULL_RING(1) LBM_PULL_RING(2) LBM_PULL_RING(3) LBM_PULL_RING(4)
+  LBM_PULL_RING(5) LBM_PULL_RING(6) LBM_PULL_RING(7) LBM_PULL_RING(8)
+#undef LBM_PULL_RING
+}
+
+// Step-0 pulls of this wavefront's row in iteration it, into d; false if
+// the row is past the segment's window or the lane's node lies beyond a wall.
+template <typename S, int NS, int NW>
+__device__ __forceinline__ bool strip_fetch(const KArgs<typename Codec<S>::R>& a, const S* __restrict__ src,
+                                            int it, int ys, int ye, int w, int wx, int& gx, int& gy,
+                                            typename Codec<S>::R d[9]) {
+  const int r0 = ys - (NS - 1) + it * NW + w;
+  if (r0 >= ye + NS - 1) return false;
+  if (!window_node(a.g, wx, r0, gx, gy)) return false;
+  gather<S>(a.g, a.wadd, src, gx, gy, d);
+  return true;
+}
+
+// Strip walk of a workgroup whose window touches a wall or wraps: every
+// node resolves its links and wrapped position as the single step does.
+// The step-0 pulls of iteration it + 1 are issued before the work of
+// iteration it.
+template <typename S, int FM, bool SR, int NS, int NW, int RING>
+__device__ __forceinline__ void strip_walk_edge(const KArgs<typename Codec<S>::R>& a,
+                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
+                                                S* __restrict__ dst, const uint32_t (&key)[3], int x0, int ys,
+                                                int ye, S (&rg)[NS - 1][9][RING][64]) {
+  using R = typename Codec<S>::R;
+  const Geom& g = a.g;
+  const int lane = (int)threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int wx = x0 - (NS - 1) + lane;  // window column of this lane (unwrapped)
+  const int nit = (ye - ys + 2 * (NS - 1) + NW - 1) / NW;
+  R dc[9];
+  int gxc = 0, gyc = 0;
+  bool lc = strip_fetch<S, NS, NW>(a, src, 0, ys, ye, w, wx, gxc, gyc, dc);
+  for (int it = 0; it < nit; ++it) {
+    const int r0 = ys - (NS - 1) + it * NW + w;  // wavefront-uniform
+    R dn[9];
+    int gxn = 0, gyn = 0;
+    const bool ln = it + 1 < nit && strip_fetch<S, NS, NW>(a, src, it + 1, ys, ye, w, wx, gxn, gyn, dn);
+    if (lc) {
+      R Fx, Fy;
+      force_at<FM>(a, gxc, gyc, Fx, Fy);
+      R out[9];
+      collide_step<R, FM != 0>(rt, Fx, Fy, dc, out);
+      S o[9];
+      round_out<S, SR>(out, (uint32_t)(gyc * g.nx + gxc), key[0], o);
+      const int sl = ring_slot<RING>(r0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) rg[0][k][sl][lane] = o[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 1; s < NS; ++s) {
+      const int r = r0 - s;
+      if (r >= ys - (NS - 1 - s) && r < ye + (NS - 1 - s) && lane >= s && lane < 64 - s) {
+        int gx = wx, gy = r;
+        bool live = window_node(g, wx, r, gx, gy);
+        if (s == NS - 1) live = live && wx < g.nx;  // ragged last strip: no output past the domain
+        if (live) {
+          R d[9];
+          pull_ring<true, S, R, RING>(a, gx, gy, rg[s - 1], lane, ring_slot<RING>(r - 1), ring_slot<RING>(r),
+                                      ring_slot<RING>(r + 1), d);
+          R Fx, Fy;
+          force_at<FM>(a, gx, gy, Fx, Fy);
+          R out[9];
+          collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+          S o[9];
+          round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key[s], o);
+          if (s < NS - 1) {
+            const int sl = ring_slot<RING>(r);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) rg[s < NS - 1 ? s : 0][k][sl][lane] = o[k];
+          } else {
+            const int64_t c = (int64_t)gy * g.pitch + gx;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) dst[(int64_t)k * g.plane + c] = o[k];
+          }
+        }
+      }
+      if (s < NS - 1) __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dc[k] = dn[k];
+    gxc = gxn;
+    gyc = gyn;
+    lc = ln;
+  }
+}
+
+// Interior strip walk on the buffer path: no node of the window has a wall
+// link or wraps, and the lattice is below 4 GiB.  The step-0 pulls run two
+// iterations ahead of their use and are issued at the start of an iteration,
+// before its stores, in every iteration and for every lane (the row clamped
+// to the window), so that no path through the loop skips a load: the wait for
+// a set of pulls then covers only memory operations at least one iteration
+// old.  The loop is unrolled three times over three register sets, one per
+// iteration in flight.  Step 0 also runs on the rows of the padding
+// iterations past the window; those rows land in ring slots no live row
+// needs and are never read.
+template <typename S, int FM, bool SR, int NS, int NW, int RING>
+__device__ __forceinline__ void strip_walk_fast(const KArgs<typename Codec<S>::R>& a,
+                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
+                                                S* __restrict__ dst, const uint32_t (&key)[3], int x0, int ys,
+                                                int ye, S (&rg)[NS - 1][9][RING][64]) {
+  using R = typename Codec<S>::R;
+  const Geom& g = a.g;
+  const int lane = (int)threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int wx = x0 - (NS - 1) + lane;
+  const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
+  const __amdgpu_buffer_rsrc_t wr = rsrc(dst, g.lattice_bytes);
+  const int rlast = ye + NS - 2;  // last step-0 row of the window
+  const int nit = (ye - ys + 2 * (NS - 1) + NW - 1) / NW;
+  const int nit3 = (nit + 2) / 3 * 3;
+  auto fetch = [&](int it, R (&d)[9]) {
+    const int r = min(ys - (NS - 1) + it * NW + w, rlast);
+    const uint32_t off = (uint32_t)(r * g.pitch + wx) * (uint32_t)sizeof(S);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
+  };
+  auto body = [&](int it, const R (&dc)[9], R (&dn)[9]) {
+    fetch(it + 2, dn);
+    const int r0 = ys - (NS - 1) + it * NW + w;  // wavefront-uniform
+    {
+      const int gy = min(r0, rlast);
+      R Fx, Fy;
+      force_at<FM>(a, wx, gy, Fx, Fy);
+      R out[9];
+      collide_step<R, FM != 0>(rt, Fx, Fy, dc, out);
+      S o[9];
+      round_out<S, SR>(out, (uint32_t)(gy * g.nx + wx), key[0], o);
+      const int sl = ring_slot<RING>(r0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) rg[0][k][sl][lane] = o[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 1; s < NS; ++s) {
+      const int r = r0 - s;
+      if (r >= ys - (NS - 1 - s) && r < ye + (NS - 1 - s) && lane >= s && lane < 64 - s) {
+        R d[9];
+        pull_ring<false, S, R, RING>(a, wx, r, rg[s - 1], lane, ring_slot<RING>(r - 1), ring_slot<RING>(r),
+                                     ring_slot<RING>(r + 1), d);
+        R Fx, Fy;
+        force_at<FM>(a, wx, r, Fx, Fy);
+        R out[9];
+        collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+        S o[9];
+        round_out<S, SR>(out, (uint32_t)(r * g.nx + wx), key[s], o);
+        if (s < NS - 1) {
+          const int sl = ring_slot<RING>(r);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) rg[s < NS - 1 ? s : 0][k][sl][lane] = o[k];
+        } else {
+          const uint32_t off = (uint32_t)(r * g.pitch + wx) * (uint32_t)sizeof(S);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(wr, off, g.st_soff[k], o[k]);
+        }
+      }
+      if (s < NS - 1) __syncthreads();
+    }
+  };
+  R p0[9], p1[9], p2[9];
+  fetch(0, p0);
+  __builtin_amdgcn_sched_barrier(0);  // keep the pulls of iteration 0 the older ones
+  fetch(1, p1);
+  for (int it = 0; it < nit3; it += 3) {
+    body(it, p0, p2);
+    body(it + 1, p1, p0);
+    body(it + 2, p2, p1);
+  }
+}
+
+// NS (2 or 3) fused steps per launch, strip tiling (see above); the grid has
+// st.strips * st.segs workgroups.
+template <typename S, int FM, bool SR, int NS, int NW, int RING>
+__global__ __launch_bounds__(64 * NW) void k_strip(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                                   S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
+                                                   uint32_t key_c) {
+  static_assert(NS == 2 || NS == 3, "two or three fused steps");
+  static_assert(RING >= (NS == 2 ? 2 * NW + 2 : NW + 2), "ring too short for the rows alive at once");
+  constexpr int TW = 64 - 2 * (NS - 1);
+  __shared__ S rg[NS - 1][9][RING][64];
+  const Geom& g = a.g;
+  const StripTiling& t = NS == 3 ? g.st3 : g.st2;
+  const auto rt = rates(a);
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int x0 = (tile % t.strips) * TW;
+  const int ys = (tile / t.strips) * t.len;
+  const int ye = min(ys + t.len, g.ny);
+  const uint32_t key[3] = {key_a, key_b, key_c};
+  // interior: every window node lies in [1, n - 2] in both directions, so no
+  // link of any node the workgroup computes crosses a wall or wraps.
+  const bool interior = x0 - (NS - 1) >= 1 && x0 + 64 - NS <= g.nx - 2 && ys - (NS - 1) >= 1 &&
+                        ye + NS - 2 <= g.ny - 2;
+  if (interior && g.fast)  // workgroup-uniform: every wavefront meets the same barriers
+    strip_walk_fast<S, FM, SR, NS, NW, RING>(a, rt, src, dst, key, x0, ys, ye, rg);
+  else
+    strip_walk_edge<S, FM, SR, NS, NW, RING>(a, rt, src, dst, key, x0, ys, ye, rg);
 }
 
 // Initial state f-bar = f^eq - S/2 (transformed equilibrium with hF = -F/2).
@@ -1036,6 +1286,41 @@ hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t 
       return launch_step3_fm<float, false, kStep3TyF32, kStep3ThreadsF32>(a.f, src, dst, key_a, key_b, key_c, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <bool SR>
+static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void* dst, uint32_t ka, uint32_t kb,
+                                   uint32_t kc, hipStream_t st) {
+  constexpr int NW = kStripWaves, RING = kStripRing;
+  const StripTiling& t = k.g.st3;
+  if (t.len < 1 || t.strips < 1 || t.segs < 1 || (int64_t)t.len * t.segs < k.g.ny ||
+      (int64_t)t.strips * 60 < k.g.nx)
+    return hipErrorInvalidValue;
+  const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
+  const dim3 grid((unsigned)(t.strips * t.segs)), block(64 * NW);
+  using S = float;
+  if (fm == 0)
+    hipLaunchKernelGGL((k_strip<S, 0, SR, 3, NW, RING>), grid, block, 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+  else if (fm == 1)
+    hipLaunchKernelGGL((k_strip<S, 1, SR, 3, NW, RING>), grid, block, 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+  else
+    hipLaunchKernelGGL((k_strip<S, 2, SR, 3, NW, RING>), grid, block, 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+  return hipGetLastError();
+}
+
+hipError_t launch_strip3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                         uint32_t key_c, hipStream_t st) {
+  if (a.storage != 1) return hipErrorInvalidValue;
+  return launch_strip3_fm<false>(a.f, src, dst, key_a, key_b, key_c, st);
+}
+
+int strip3_resident() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per, k_strip<float, 0, false, 3, kStripWaves, kStripRing>, 64 * kStripWaves, 0);
+  return e == hipSuccess ? cus * per : 0;
 }
 
 hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t key, hipStream_t st) {

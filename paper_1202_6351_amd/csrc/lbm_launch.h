@@ -7,6 +7,12 @@
 
 namespace lbm {
 
+// Strip tiling of the fused kernels: strips of 64 - 2 (steps - 1) columns,
+// cut into segs segments of len rows (the last one may be shorter).
+struct StripTiling {
+  int32_t len, strips, segs;
+};
+
 // Lattice geometry and launch tiling.
 struct Geom {
   int32_t nx, ny;
@@ -26,6 +32,7 @@ struct Geom {
   // workgroup.
   int32_t t2_ty, t2_tiles_x, t2_tiles_y;
   int32_t t3_ty, t3_tiles_x, t3_tiles_y, t3_threads;
+  StripTiling st2, st3;
 };
 
 // Three-step kernel shapes: output tile 64 x TY, NT threads per workgroup
@@ -36,6 +43,18 @@ constexpr int kStep3TyF32 = 12, kStep3ThreadsF32 = 256;
 constexpr int kStep3TyF64 = 4, kStep3ThreadsF64 = 256;
 constexpr int kStep3TyF64Large = 10, kStep3ThreadsF64Large = 512;
 constexpr int64_t kStep3LargeMinNodes = 1 << 20;
+
+// Three-step strip kernel (FP32): wavefronts per workgroup, ring rows per
+// intermediate step, and its segment length: the launch is cut into about
+// kStripRounds waves of resident workgroups (segments per strip =
+// kStripRounds x resident workgroups / strips), segments at least
+// kStripMinLen rows.  FP32 lattices of up to kStripMaxNodes nodes take the
+// strip kernel; larger ones, and FP64, the 64 x TY tiles (measured on one
+// MI355X: strips lead up to 2048^2, tiles from 2896^2 up, and for FP64 at
+// every size).
+constexpr int kStripWaves = 4, kStripRing = 6;
+constexpr int kStripRounds = 16, kStripMinLen = 8;
+constexpr int64_t kStripMaxNodes = (int64_t)6 << 20;
 
 // Two-step adjoint tile heights (64 x TY tiles, 256 threads).
 constexpr int kAdjoint2TyF32 = 8, kAdjoint2TyF64 = 4;
@@ -79,6 +98,13 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
 // calls.
 hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                         uint32_t key_c, hipStream_t st);
+// Strip-tiled three-step launch (FP32 only): same contract as launch_step3;
+// the tiling is g.st3.
+hipError_t launch_strip3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                         uint32_t key_c, hipStream_t st);
+// Workgroups of the three-step strip kernel resident on the current device at
+// once (compute units x workgroups per unit); 0 if the device query fails.
+int strip3_resident();
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);

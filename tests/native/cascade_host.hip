@@ -5,11 +5,7 @@
 
 namespace {
 lbm::Rates<double> rates_of(const double* w, double rho0) {
-  lbm::Rates<double> r;
-  r.w3 = w[0]; r.w4 = w[1]; r.w5 = w[2]; r.w6 = w[3]; r.w7 = w[4]; r.w8 = w[5];
-  r.k3 = 1 - r.w3; r.k4 = 1 - r.w4; r.k5 = 1 - r.w5; r.k6 = 1 - r.w6; r.k7 = 1 - r.w7; r.k8 = 1 - r.w8;
-  r.rho0 = rho0;
-  return r;
+  return lbm::make_rates<double>(w, rho0);
 }
 }  // namespace
 

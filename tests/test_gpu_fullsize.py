@@ -143,6 +143,42 @@ def test_cavity_4096_three_step_launch(storage, tol):
     assert err.max() <= tol
 
 
+@pytest.mark.parametrize("shape", [(2500, 2515), (2600, 2597)])
+@pytest.mark.parametrize("case", ["cavity", "periodic_force"])
+def test_fp32_three_step_kernels_either_side_of_switch(shape, case):
+    """FP32 three-step launches take the strip kernel up to 6 Mi nodes and the
+    64 x TY tiles above: 2500 x 2515 (6287500 nodes) and 2600 x 2597
+    (6752200), both ragged in x and y, each bit-exact against three single
+    steps; the cavity case also within 4e-7 of three FP64 oracle steps at
+    sampled nodes."""
+    from paper_1202_6351_amd import Lattice, Params
+    nx, ny = shape
+    if case == "cavity":
+        tau = W.cavity_tau(nx, 0.1, 1000.0)
+        kw = dict(bc=("wall",) * 4, wall_u=(0, 0, 0, 0.1))
+        fields = W.at_rest(nx, ny, density_noise=1e-6, seed=2)
+    else:
+        tau = 0.7
+        kw = dict(fx=2e-6, fy=-1e-6)
+        fields = W.at_rest(nx, ny, density_noise=1e-4, seed=3)
+    lat = Lattice(Params(nx, ny, tau=tau, storage="fp32", **kw), device="cuda:0")
+    lat.init_equilibrium(*fields)
+    lat.step(30)
+    _fused_equals_single(lat, 3)
+    if case != "cavity":
+        return
+    f_n = lat.populations().cpu().numpy()
+    lat.step(3)
+    p = oracle.Params(nx, ny, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
+    want_all = oracle.step(p, f_n, 3)
+    del f_n
+    xs, ys = _sample_nodes(nx, ny, 2000, seed=7)
+    got = lat.populations()[:, torch.from_numpy(ys).long().cuda(), torch.from_numpy(xs).long().cuda()].cpu().numpy()
+    err = np.abs(got - want_all[:, ys, xs])
+    print(f"fp32 {nx}x{ny}: max three-step error {err.max():.3e} over {len(xs)} nodes")
+    assert err.max() <= 4e-7
+
+
 @pytest.mark.parametrize("storage,rounding", [("fp16", "nearest"), ("bf16", "stochastic")])
 def test_taylor_green_8192_two_step_launch(storage, rounding):
     """The 16-bit forms' launch (two steps, Taylor-Green 8192^2) equals two
