@@ -109,6 +109,7 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
   const int64_t esz = storage_size(p->storage);
   const int64_t total = 9 * g.plane * esz;
   g.fast = total < ((int64_t)1 << 32);
+  g.wb_stores = 2 * total <= lbm::kWriteBackMaxBytes;
   g.lattice_bytes = g.fast ? (uint32_t)total : 0u;
   for (int k = 0; k < 9; ++k) {
     // plane k read at (x - e_x, y - e_y): offset k*plane - e_y*pitch - e_x, >= 0

@@ -254,6 +254,34 @@ template <> struct BufIO<__bf16> {
   }
 };
 
+// The nine stored values of node (x, y) into lattice dst.  Non-temporal
+// stores stream a large lattice past the caches; a lattice whose pair fits in
+// the last-level cache (g.wb_stores) is written back through them, so the next
+// launch reads it from there.
+template <typename S>
+__device__ __forceinline__ void store_node(const Geom& g, S* __restrict__ dst, int x, int y, const S o[9]) {
+  if (g.fast) {
+    const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
+    const uint32_t off = (uint32_t)(y * g.pitch + x) * (uint32_t)sizeof(S);
+    if (g.wb_stores) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(w, off, g.st_soff[k], o[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], o[k]);
+    }
+  } else {
+    const int64_t c = (int64_t)y * g.pitch + x;
+    if (g.wb_stores) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) dst[(int64_t)k * g.plane + c] = o[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
+    }
+  }
+}
+
 // Stores of one node's nine post-collision values as the storage type, with
 // the step's rounding: nearest even, or stochastic with 16 random bits per
 // population from a chain of PCG hashes keyed by the node and the step.
@@ -309,15 +337,7 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, con
   collide_step<R, FM != 0>(rates(a), Fx, Fy, d, out);
   S o[9];
   round_out<S, SR>(out, (uint32_t)(p.y * g.nx + p.x), key, o);
-  if (g.fast) {
-    const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], o[k]);
-  } else {
-    const int64_t c = (int64_t)p.y * g.pitch + p.x;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
-  }
+  store_node<S>(g, dst, p.x, p.y, o);
 }
 
 // ---- multi-step launches (temporal blocking) ----------------------------
@@ -528,16 +548,7 @@ __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& 
     collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
     S o[9];
     round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key, o);
-    if (g.fast) {
-      const __amdgpu_buffer_rsrc_t w = rsrc(dst, g.lattice_bytes);
-      const uint32_t off = (uint32_t)(gy * g.pitch + gx) * (uint32_t)sizeof(S);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) BufIO<S>::store(w, off, g.st_soff[k], o[k]);
-    } else {
-      const int64_t c = (int64_t)gy * g.pitch + gx;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(o[k], dst + (int64_t)k * g.plane + c);
-    }
+    store_node<S>(g, dst, gx, gy, o);
   }
 }
 
@@ -1294,7 +1305,7 @@ static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void*
   constexpr int NW = kStripWaves, RING = kStripRing;
   const StripTiling& t = k.g.st3;
   if (t.len < 1 || t.strips < 1 || t.segs < 1 || (int64_t)t.len * t.segs < k.g.ny ||
-      (int64_t)t.strips * 60 < k.g.nx)
+      (int64_t)t.strips * (64 - 2 * 2) < k.g.nx)
     return hipErrorInvalidValue;
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(t.strips * t.segs)), block(64 * NW);

@@ -25,6 +25,7 @@ struct Geom {
   // from the lattice base, for the pull read (shifted by -e_a) and for the
   // store (unshifted).
   int32_t fast;            // 1 if the byte offsets below fit in 32 bits
+  int32_t wb_stores;       // 1: write-back stores (the lattice pair fits kWriteBackMaxBytes)
   uint32_t lattice_bytes;  // 9 * plane * sizeof(storage) (when fast)
   uint32_t ld_soff[9];
   uint32_t st_soff[9];
@@ -55,6 +56,11 @@ constexpr int64_t kStep3LargeMinNodes = 1 << 20;
 constexpr int kStripWaves = 4, kStripRing = 6;
 constexpr int kStripRounds = 16, kStripMinLen = 8;
 constexpr int64_t kStripMaxNodes = (int64_t)6 << 20;
+
+// Step kernels write a lattice back through the caches (instead of
+// streaming it past them) when both lattices together take at most this many
+// bytes, so that the next launch finds the state in the last-level cache.
+constexpr int64_t kWriteBackMaxBytes = (int64_t)192 << 20;
 
 // Two-step adjoint tile heights (64 x TY tiles, 256 threads).
 constexpr int kAdjoint2TyF32 = 8, kAdjoint2TyF64 = 4;
