@@ -9,8 +9,9 @@
 // scheme).  One thread owns one node.  A step gathers the nine populations
 // streaming into the node (plane a at x - e_a: coalesced, misaligned by one
 // element for e_x != 0), collides in registers (cascade.h) and writes the
-// nine results to the other lattice at the node itself (aligned, coalesced,
-// non-temporal).  A link whose source lies beyond a wall reads the reversed
+// nine results to the other lattice at the node itself (aligned, coalesced;
+// non-temporal, or write-back when both lattices fit in the last-level
+// cache).  A link whose source lies beyond a wall reads the reversed
 // population of the node itself (halfway bounce-back) plus the moving-wall
 // term; walls are resolved per thread from (x, y) with selects, so there is
 // no mask array and the wall rows do not diverge from the interior.
