@@ -11,8 +11,9 @@
  * ---------------------------------------
  * Memory.  Every pointer argument named as a device buffer is device memory
  *   owned by the caller (the library never frees it); the library itself
- *   owns only the context and a small reduction scratch area allocated in
- *   lbm_create.  Host pointers are named as such.
+ *   owns only the context and a small reduction scratch area allocated by
+ *   the first lbm_diagnostics call (creating and destroying a context that
+ *   never asks for diagnostics allocates no device memory).  Host pointers are named as such.
  * Streams.  All calls are asynchronous on the context's HIP stream, except
  *   lbm_diagnostics (synchronises that stream) and lbm_lattice_layout /
  *   lbm_create / lbm_destroy (host only).  A caller that reads a buffer on
@@ -135,9 +136,12 @@ lbm_status lbm_lattice_layout(const lbm_params* p, int64_t* pitch, int64_t* byte
  * lbm_lattice_layout bytes each).  force_field is NULL (uniform fx, fy) or a
  * device R array [2][ny][nx] (F_x plane then F_y plane), read by every step.
  * stream is a hipStream_t (NULL = default stream).  Validates p (EINVAL) and
- * allocates the context and its reduction scratch (EDEVICE on failure).  On
- * success *out owns them until lbm_destroy.  The state is undefined until
- * lbm_init_equilibrium or lbm_set_populations. */
+ * allocates the context (host memory; EDEVICE on failure).  On success *out
+ * owns it, and the scratch area it may allocate, until lbm_destroy.  The
+ * state is undefined until lbm_init_equilibrium or lbm_set_populations.
+ * Several contexts may share lat0/lat1 (each on its own stream, say); the
+ * calls that take explicit buffers (lbm_step_sequence, lbm_step_between and
+ * the adjoint calls) never touch a context's own lattices. */
 lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1,
                       const void* force_field, void* stream, lbm_ctx** out);
 
@@ -216,7 +220,9 @@ lbm_status lbm_macroscopic(lbm_ctx* ctx, void* rho, void* ux, void* uy,
 /* Global sums of the current state, accumulated in FP64 with a fixed
  * reduction order (deterministic): out[0] = sum rho, out[1] = sum rho ux,
  * out[2] = sum rho uy, out[3] = 1/2 sum rho |u|^2 (host array of 4).
- * Synchronises the stream.  Returns LBM_EUNSTABLE if any sum is not finite. */
+ * Synchronises the stream.  The first call on a context allocates its
+ * reduction scratch area (33 KB of device memory; EDEVICE on failure).
+ * Returns LBM_EUNSTABLE if any sum is not finite. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, double out[4]);
 
 /* Adjoint (vector-Jacobian product) of one step n-1 -> n.  lat_prev: the

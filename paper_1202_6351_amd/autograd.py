@@ -14,10 +14,12 @@ initial-state map.
 Memory: the forward keeps a lattice snapshot every `checkpoint_every` steps.
 The backward recomputes each segment's states from its snapshot and runs the
 adjoint over them newest-first.  The recompute of the next (older) segment
-runs on a second stream while the adjoint of the current one runs, so the
-two kernels share the GPU; they alternate between two sets of
-`checkpoint_every - 1` lattice buffers.  Work per step of the backward: one
-recomputed step and one adjoint step.
+runs on one stream while the adjoint of the current one runs on another, so
+the two kernels share the GPU; they alternate between two sets of
+`checkpoint_every - 1` lattice buffers.  Both streams are ordinary streams
+kept per device (not the legacy default stream, whose implicit
+synchronisation with other streams serialised the two).  Work per step of
+the backward: one recomputed step and one adjoint step.
 """
 from __future__ import annotations
 
@@ -26,6 +28,17 @@ from typing import Optional
 import torch
 
 from .lattice import Lattice, Params
+
+
+_BACKWARD_STREAMS = {}
+
+
+def _backward_streams(dev: torch.device):
+    """(adjoint stream, recompute stream) of a device, created once."""
+    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    if key not in _BACKWARD_STREAMS:
+        _BACKWARD_STREAMS[key] = (torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev))
+    return _BACKWARD_STREAMS[key]
 
 
 class Rollout(torch.autograd.Function):
@@ -76,18 +89,30 @@ class Rollout(torch.autograd.Function):
         snaps = ctx.snaps
         nseg = len(snaps)
         seg_len = [max(min(every, steps - s * every), 0) for s in range(nseg)]
-        main = lat.stream
-        side = torch.cuda.Stream(device=dev)
-        side.wait_stream(main)  # the snapshots are written on the main stream
-        # Recomputes run on `side` through a second context (same problem,
-        # same force field).  A segment of n steps needs its snapshot and the
-        # n - 1 states after it; the state after the last step of the last
-        # segment is the forward lattice's current state.
-        rec = Lattice(p, device=dev, force=lat.force, stream=side)
         width = max(min(every, max(steps, 0)) - 1, 0)
         sets = [[torch.empty_like(lat.lat[0]) for _ in range(width)] for _ in range(2)]
-        for t in [*snaps, *sets[0], *sets[1], lat.force]:
-            t.record_stream(side)
+        rho, ux0, uy0 = ctx.init_fields
+        g_ux0 = torch.empty_like(ux0, dtype=real)
+        g_uy0 = torch.empty_like(uy0, dtype=real)
+        # Adjoint calls run on `main`, recomputes on `side`, each through a
+        # context of its own over the forward's buffers and force field.  A
+        # segment of n steps needs its snapshot and the n - 1 states after
+        # it; the state after the last step of the last segment is the
+        # forward lattice's current state.  Both streams start after the
+        # forward's stream (snapshots, final state) and the caller's (the
+        # loss cotangents and every buffer allocated above).
+        caller = torch.cuda.current_stream(dev)
+        main, side = _backward_streams(dev)
+        for st in (main, side):
+            st.wait_stream(lat.stream)
+            st.wait_stream(caller)
+        for t in (*snaps, *sets[0], *sets[1], lat.force, lat.current, grad_force, mu, mu2, g_rho, g_ux, g_uy,
+                  g_ux0, g_uy0, rho, ux0, uy0):
+            if t is not None:
+                t.record_stream(side)
+                t.record_stream(main)
+        adj = lat.on_stream(main)
+        rec = lat.on_stream(side)
         ready = [torch.cuda.Event(), torch.cuda.Event()]
         free = [None, None]
 
@@ -101,24 +126,23 @@ class Rollout(torch.autograd.Function):
                 ready[b].record(side)
 
         recompute(nseg - 1, 0)
-        for k, s in enumerate(range(nseg - 1, -1, -1)):
-            b = k % 2
-            if s > 0:
-                recompute(s - 1, 1 - b)
-            main.wait_event(ready[b])
-            n = seg_len[s]
-            states = [snaps[s]] + sets[b][:max(n - 1, 0)]
-            if s == nseg - 1:
-                lat.adjoint_macroscopic(lat.current, g_rho, g_ux, g_uy, mu, grad_force)
-            if lat.adjoint_sequence(states[:n], mu, mu2, grad_force) is mu2:
-                mu, mu2 = mu2, mu
-            free[b] = torch.cuda.Event()
-            free[b].record(main)
-        main.wait_stream(side)
-        rho, ux0, uy0 = ctx.init_fields
-        g_ux0 = torch.empty_like(ux0, dtype=real)
-        g_uy0 = torch.empty_like(uy0, dtype=real)
-        lat.adjoint_init(rho, ux0, uy0, mu, None, g_ux0, g_uy0, grad_force)
+        with torch.cuda.stream(main):
+            for k, s in enumerate(range(nseg - 1, -1, -1)):
+                b = k % 2
+                if s > 0:
+                    recompute(s - 1, 1 - b)
+                main.wait_event(ready[b])
+                n = seg_len[s]
+                states = [snaps[s]] + sets[b][:max(n - 1, 0)]
+                if s == nseg - 1:
+                    adj.adjoint_macroscopic(lat.current, g_rho, g_ux, g_uy, mu, grad_force)
+                if adj.adjoint_sequence(states[:n], mu, mu2, grad_force) is mu2:
+                    mu, mu2 = mu2, mu
+                free[b] = torch.cuda.Event()
+                free[b].record(main)
+            main.wait_stream(side)
+            adj.adjoint_init(rho, ux0, uy0, mu, None, g_ux0, g_uy0, grad_force)
+        caller.wait_stream(main)
         ctx.lat = ctx.snaps = None
         return grad_force, torch.stack([g_ux0, g_uy0]), None, None, None, None
 

@@ -21,7 +21,7 @@ struct lbm_ctx {
   bool has_state;
   bool has_force_field;
   hipStream_t stream;
-  double* diag_scratch;  // device: partial sums (diag_blocks * 4) + result (4)
+  double* diag_scratch;  // device: partial sums (diag_blocks * 4) + result (4); first diagnostics call
   int diag_blocks;
   int64_t pitch, lattice_bytes;
   bool strip3;        // three-step launches take the strip kernel (else 64 x TY tiles)
@@ -249,12 +249,7 @@ lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* f
   // Diagnostics: a fixed number of blocks (enough to fill 256 CUs), so the
   // reduction order does not depend on the grid size.
   c->diag_blocks = 1024;
-  hipError_t e = hipMalloc((void**)&c->diag_scratch, sizeof(double) * (c->diag_blocks * 4 + 4));
-  if (e != hipSuccess) {
-    set_err(g_create_err, "hipMalloc(diagnostics scratch): %s", hipGetErrorString(e));
-    delete c;
-    return LBM_EDEVICE;
-  }
+  c->diag_scratch = nullptr;  // allocated by the first lbm_diagnostics call
   c->err[0] = 0;
   *out = c;
   return LBM_OK;
@@ -402,6 +397,14 @@ lbm_status lbm_diagnostics(lbm_ctx* c, double out[4]) {
   if (!c) return LBM_EINVAL;
   if (!out) return inval(c, "diagnostics: out is NULL");
   if (!c->has_state) { set_err(c->err, "diagnostics before the state was set"); return LBM_ESTATE; }
+  if (!c->diag_scratch) {
+    const hipError_t e = hipMalloc((void**)&c->diag_scratch, sizeof(double) * (c->diag_blocks * 4 + 4));
+    if (e != hipSuccess) {
+      c->diag_scratch = nullptr;
+      set_err(c->err, "hipMalloc(diagnostics scratch): %s", hipGetErrorString(e));
+      return LBM_EDEVICE;
+    }
+  }
   double* res = c->diag_scratch + 4 * c->diag_blocks;
   const double base = (double)c->p.nx * (double)c->p.ny * c->p.rho0;
   lbm_status s = dev_err(c, lbm::launch_diag(c->args, c->lat[c->cur], c->diag_scratch, c->diag_blocks, base, res,

@@ -115,6 +115,23 @@ class Lattice:
         self._ctx = ctx
         self._destroy = _lib.lib().lbm_destroy  # kept: module globals may be gone at exit
 
+    def on_stream(self, stream: torch.cuda.Stream) -> "Lattice":
+        """Another handle on this lattice's buffers and force field whose
+        library calls launch on `stream` (a context of its own).  Meant for
+        the calls that take explicit buffers (step_sequence, step_between,
+        the adjoint calls), so that two streams can work on one problem at
+        once; its time starts at 0 and it has no state until one is set."""
+        v = Lattice.__new__(Lattice)
+        v.params, v.device, v.pitch, v.nbytes = self.params, self.device, self.pitch, self.nbytes
+        v.lat, v.real, v.force, v.stream = self.lat, self.real, self.force, stream
+        ctx = ctypes.c_void_p()
+        cp = self.params.c()
+        _lib.check(_lib.lib().lbm_create(ctypes.byref(cp), _ptr(v.lat[0]), _ptr(v.lat[1]), _ptr(v.force),
+                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(ctx)))
+        v._ctx = ctx
+        v._destroy = _lib.lib().lbm_destroy
+        return v
+
     # ----------------------------------------------------------- plumbing
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
