@@ -195,9 +195,11 @@ lbm_status lbm_step_between(lbm_ctx* ctx, const void* src, void* dst);
 /* n >= 0 single steps that keep every state: states[0] = step(src),
  * states[i] = step(states[i-1]).  states: host array of n device lattice
  * buffers of this context's layout, 256-byte aligned, none equal to its
- * input (src for states[0], states[i-1] for states[i]).  The segment
- * recompute of a checkpointed adjoint.  Same result as n calls of
- * lbm_step_between.  Does not change lbm_time or the current lattice. */
+ * input (src for states[0], states[i-1] for states[i]); a buffer may be
+ * reused once its state has been read (ping-pong).  The segment recompute
+ * of a checkpointed adjoint.  Same result as n calls of lbm_step_between
+ * (groups of three steps whose four buffers are distinct may run as one
+ * fused launch).  Does not change lbm_time or the current lattice. */
 lbm_status lbm_step_sequence(lbm_ctx* ctx, const void* src, void* const* states, int64_t n);
 
 /* Copy the current lattice to dst (snapshot) / src to the current lattice

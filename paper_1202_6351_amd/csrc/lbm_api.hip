@@ -356,9 +356,21 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
     if (!states[i] || states[i] == prev) return inval(c, "step_sequence: states[i] NULL or equal to its input");
     if (!aligned(states[i])) return inval(c, "step_sequence: buffers must be 256-byte aligned");
   }
-  for (int64_t i = 0; i < n; ++i) {
-    lbm_status s = dev_err(c, lbm::launch_step(c->args, i == 0 ? src : states[i - 1], states[i],
-                                               step_key(c->p, c->t), c->stream),
+  // FP32 lattices that take the strip kernel run groups of three steps as
+  // one launch that also stores the two intermediate states, as long as the
+  // group's four buffers are distinct; the rest runs as single steps.
+  const uint32_t key = step_key(c->p, c->t);
+  int64_t i = 0;
+  for (; c->strip3 && i + 3 <= n; i += 3) {
+    const void* in = i == 0 ? src : states[i - 1];
+    void *k0 = states[i], *k1 = states[i + 1], *out = states[i + 2];
+    if (in == k1 || in == out || k0 == k1 || k0 == out || k1 == out) break;  // in != k0 checked above
+    lbm_status s = dev_err(c, lbm::launch_strip3_keep(c->args, in, k0, k1, out, key, key, key, c->stream),
+                           "three-step kernel");
+    if (s != LBM_OK) return s;
+  }
+  for (; i < n; ++i) {
+    lbm_status s = dev_err(c, lbm::launch_step(c->args, i == 0 ? src : states[i - 1], states[i], key, c->stream),
                            "step kernel");
     if (s != LBM_OK) return s;
   }

@@ -283,6 +283,15 @@ __device__ __forceinline__ void store_node(const Geom& g, S* __restrict__ dst, i
   }
 }
 
+// The nine values of node (x, y) into a kept intermediate state, written
+// back through the caches (the state is read again soon).
+template <typename S>
+__device__ __forceinline__ void store_kept(const Geom& g, S* __restrict__ dst, int x, int y, const S o[9]) {
+  const int64_t c = (int64_t)y * g.pitch + x;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dst[(int64_t)k * g.plane + c] = o[k];
+}
+
 // Stores of one node's nine post-collision values as the storage type, with
 // the step's rounding: nearest even, or stochastic with 16 random bits per
 // population from a chain of PCG hashes keyed by the node and the step.
@@ -682,11 +691,11 @@ __device__ __forceinline__ bool strip_fetch(const KArgs<typename Codec<S>::R>& a
 // node resolves its links and wrapped position as the single step does.
 // The step-0 pulls of iteration it + 1 are issued before the work of
 // iteration it.
-template <typename S, int FM, bool SR, int NS, int NW, int RING>
+template <typename S, int FM, bool SR, int NS, int NW, int RING, bool KEEP>
 __device__ __forceinline__ void strip_walk_edge(const KArgs<typename Codec<S>::R>& a,
                                                 const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
-                                                S* __restrict__ dst, const uint32_t (&key)[3], int x0, int ys,
-                                                int ye, S (&rg)[NS - 1][9][RING][64]) {
+                                                S* __restrict__ dst, S* const (&keep)[2], const uint32_t (&key)[3],
+                                                int x0, int ys, int ye, S (&rg)[NS - 1][9][RING][64]) {
   using R = typename Codec<S>::R;
   const Geom& g = a.g;
   const int lane = (int)threadIdx.x & 63;
@@ -711,6 +720,8 @@ __device__ __forceinline__ void strip_walk_edge(const KArgs<typename Codec<S>::R
       const int sl = ring_slot<RING>(r0);
 #pragma unroll
       for (int k = 0; k < 9; ++k) rg[0][k][sl][lane] = o[k];
+      if (KEEP && r0 >= ys && r0 < ye && lane >= NS - 1 && lane < 64 - (NS - 1) && wx < g.nx)
+        store_kept<S>(g, keep[0], gxc, gyc, o);
     }
     __syncthreads();
 #pragma unroll
@@ -734,6 +745,8 @@ __device__ __forceinline__ void strip_walk_edge(const KArgs<typename Codec<S>::R
             const int sl = ring_slot<RING>(r);
 #pragma unroll
             for (int k = 0; k < 9; ++k) rg[s < NS - 1 ? s : 0][k][sl][lane] = o[k];
+            if (KEEP && r >= ys && r < ye && lane >= NS - 1 && lane < 64 - (NS - 1) && wx < g.nx)
+              store_kept<S>(g, keep[s < NS - 1 ? s : 0], gx, gy, o);
           } else {
             const int64_t c = (int64_t)gy * g.pitch + gx;
 #pragma unroll
@@ -761,11 +774,11 @@ __device__ __forceinline__ void strip_walk_edge(const KArgs<typename Codec<S>::R
 // iteration in flight.  Step 0 also runs on the rows of the padding
 // iterations past the window; those rows land in ring slots no live row
 // needs and are never read.
-template <typename S, int FM, bool SR, int NS, int NW, int RING>
+template <typename S, int FM, bool SR, int NS, int NW, int RING, bool KEEP>
 __device__ __forceinline__ void strip_walk_fast(const KArgs<typename Codec<S>::R>& a,
                                                 const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
-                                                S* __restrict__ dst, const uint32_t (&key)[3], int x0, int ys,
-                                                int ye, S (&rg)[NS - 1][9][RING][64]) {
+                                                S* __restrict__ dst, S* const (&keep)[2], const uint32_t (&key)[3],
+                                                int x0, int ys, int ye, S (&rg)[NS - 1][9][RING][64]) {
   using R = typename Codec<S>::R;
   const Geom& g = a.g;
   const int lane = (int)threadIdx.x & 63;
@@ -796,6 +809,8 @@ __device__ __forceinline__ void strip_walk_fast(const KArgs<typename Codec<S>::R
       const int sl = ring_slot<RING>(r0);
 #pragma unroll
       for (int k = 0; k < 9; ++k) rg[0][k][sl][lane] = o[k];
+      if (KEEP && r0 >= ys && r0 < ye && lane >= NS - 1 && lane < 64 - (NS - 1))
+        store_kept<S>(g, keep[0], wx, r0, o);
     }
     __syncthreads();
 #pragma unroll
@@ -815,6 +830,8 @@ __device__ __forceinline__ void strip_walk_fast(const KArgs<typename Codec<S>::R
           const int sl = ring_slot<RING>(r);
 #pragma unroll
           for (int k = 0; k < 9; ++k) rg[s < NS - 1 ? s : 0][k][sl][lane] = o[k];
+          if (KEEP && r >= ys && r < ye && lane >= NS - 1 && lane < 64 - (NS - 1))
+            store_kept<S>(g, keep[s < NS - 1 ? s : 0], wx, r, o);
         } else {
           const uint32_t off = (uint32_t)(r * g.pitch + wx) * (uint32_t)sizeof(S);
 #pragma unroll
@@ -836,11 +853,12 @@ __device__ __forceinline__ void strip_walk_fast(const KArgs<typename Codec<S>::R
 }
 
 // NS (2 or 3) fused steps per launch, strip tiling (see above); the grid has
-// st.strips * st.segs workgroups.
-template <typename S, int FM, bool SR, int NS, int NW, int RING>
+// st.strips * st.segs workgroups.  KEEP: the intermediate states n+1 (and
+// n+2) are also stored, to keep0 (and keep1).
+template <typename S, int FM, bool SR, int NS, int NW, int RING, bool KEEP>
 __global__ __launch_bounds__(64 * NW) void k_strip(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
-                                                   S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
-                                                   uint32_t key_c) {
+                                                   S* __restrict__ dst, S* keep0, S* keep1, uint32_t key_a,
+                                                   uint32_t key_b, uint32_t key_c) {
   static_assert(NS == 2 || NS == 3, "two or three fused steps");
   static_assert(RING >= (NS == 2 ? 2 * NW + 2 : NW + 2), "ring too short for the rows alive at once");
   constexpr int TW = 64 - 2 * (NS - 1);
@@ -853,14 +871,15 @@ __global__ __launch_bounds__(64 * NW) void k_strip(KArgs<typename Codec<S>::R> a
   const int ys = (tile / t.strips) * t.len;
   const int ye = min(ys + t.len, g.ny);
   const uint32_t key[3] = {key_a, key_b, key_c};
+  S* const keep[2] = {keep0, keep1};
   // interior: every window node lies in [1, n - 2] in both directions, so no
   // link of any node the workgroup computes crosses a wall or wraps.
   const bool interior = x0 - (NS - 1) >= 1 && x0 + 64 - NS <= g.nx - 2 && ys - (NS - 1) >= 1 &&
                         ye + NS - 2 <= g.ny - 2;
   if (interior && g.fast)  // workgroup-uniform: every wavefront meets the same barriers
-    strip_walk_fast<S, FM, SR, NS, NW, RING>(a, rt, src, dst, key, x0, ys, ye, rg);
+    strip_walk_fast<S, FM, SR, NS, NW, RING, KEEP>(a, rt, src, dst, keep, key, x0, ys, ye, rg);
   else
-    strip_walk_edge<S, FM, SR, NS, NW, RING>(a, rt, src, dst, key, x0, ys, ye, rg);
+    strip_walk_edge<S, FM, SR, NS, NW, RING, KEEP>(a, rt, src, dst, keep, key, x0, ys, ye, rg);
 }
 
 // Initial state f-bar = f^eq - S/2 (transformed equilibrium with hF = -F/2).
@@ -1300,9 +1319,9 @@ hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t 
   }
 }
 
-template <bool SR>
-static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void* dst, uint32_t ka, uint32_t kb,
-                                   uint32_t kc, hipStream_t st) {
+template <bool SR, bool KEEP>
+static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void* dst, void* keep0, void* keep1,
+                                   uint32_t ka, uint32_t kb, uint32_t kc, hipStream_t st) {
   constexpr int NW = kStripWaves, RING = kStripRing;
   const StripTiling& t = k.g.st3;
   if (t.len < 1 || t.strips < 1 || t.segs < 1 || (int64_t)t.len * t.segs < k.g.ny ||
@@ -1311,19 +1330,29 @@ static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void*
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(t.strips * t.segs)), block(64 * NW);
   using S = float;
+  S *k0 = (S*)keep0, *k1 = (S*)keep1;
   if (fm == 0)
-    hipLaunchKernelGGL((k_strip<S, 0, SR, 3, NW, RING>), grid, block, 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_strip<S, 0, SR, 3, NW, RING, KEEP>), grid, block, 0, st, k, (const S*)src, (S*)dst, k0, k1,
+                       ka, kb, kc);
   else if (fm == 1)
-    hipLaunchKernelGGL((k_strip<S, 1, SR, 3, NW, RING>), grid, block, 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_strip<S, 1, SR, 3, NW, RING, KEEP>), grid, block, 0, st, k, (const S*)src, (S*)dst, k0, k1,
+                       ka, kb, kc);
   else
-    hipLaunchKernelGGL((k_strip<S, 2, SR, 3, NW, RING>), grid, block, 0, st, k, (const S*)src, (S*)dst, ka, kb, kc);
+    hipLaunchKernelGGL((k_strip<S, 2, SR, 3, NW, RING, KEEP>), grid, block, 0, st, k, (const S*)src, (S*)dst, k0, k1,
+                       ka, kb, kc);
   return hipGetLastError();
 }
 
 hipError_t launch_strip3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                          uint32_t key_c, hipStream_t st) {
   if (a.storage != 1) return hipErrorInvalidValue;
-  return launch_strip3_fm<false>(a.f, src, dst, key_a, key_b, key_c, st);
+  return launch_strip3_fm<false, false>(a.f, src, dst, nullptr, nullptr, key_a, key_b, key_c, st);
+}
+
+hipError_t launch_strip3_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* dst,
+                              uint32_t key_a, uint32_t key_b, uint32_t key_c, hipStream_t st) {
+  if (a.storage != 1 || !keep0 || !keep1) return hipErrorInvalidValue;
+  return launch_strip3_fm<false, true>(a.f, src, dst, keep0, keep1, key_a, key_b, key_c, st);
 }
 
 int strip3_resident() {
@@ -1331,7 +1360,7 @@ int strip3_resident() {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per, k_strip<float, 0, false, 3, kStripWaves, kStripRing>, 64 * kStripWaves, 0);
+      &per, k_strip<float, 0, false, 3, kStripWaves, kStripRing, false>, 64 * kStripWaves, 0);
   return e == hipSuccess ? cus * per : 0;
 }
 

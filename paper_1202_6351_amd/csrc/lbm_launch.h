@@ -108,6 +108,11 @@ hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t 
 // the tiling is g.st3.
 hipError_t launch_strip3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                          uint32_t key_c, hipStream_t st);
+// The same, also storing the intermediate states n+1 to keep0 and n+2 to
+// keep1 (src, keep0, keep1, dst pairwise distinct).  Same result as three
+// launch_step calls src -> keep0 -> keep1 -> dst.
+hipError_t launch_strip3_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* dst,
+                              uint32_t key_a, uint32_t key_b, uint32_t key_c, hipStream_t st);
 // Workgroups of the three-step strip kernel resident on the current device at
 // once (compute units x workgroups per unit); 0 if the device query fails.
 int strip3_resident();

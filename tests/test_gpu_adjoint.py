@@ -330,6 +330,33 @@ def test_sequences_equal_single_calls(storage, n, bci, shape):
     assert torch.equal(gf_a, gf_b)
 
 
+@pytest.mark.parametrize("pattern", ["pingpong", "cycle3", "cycle4"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_step_sequence_with_reused_buffers(pattern, storage):
+    """lbm_step_sequence may reuse a buffer once its state has been read.  In
+    FP32 the library fuses groups of three steps (storing the intermediate
+    states) only when the group's four buffers are distinct and falls back
+    to single steps otherwise: ping-pong buffers never fuse, a cycle of
+    three fuses once, a cycle of four twice.  Every buffer ends holding the
+    state last written into it, as with single steps."""
+    nx, ny = 130, 70
+    bc, wu = BCS[2]
+    lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=14), storage=storage, tau=0.65, bc=bc, wall_u=wu)
+    lat.set_populations(W.random_populations(nx, ny, seed=15, amp=0.05))
+    src = lat.snapshot()
+    n = 8
+    bufs = [lat.new_lattice() for _ in range(4)]
+    idx = {"pingpong": [0, 1] * 4, "cycle3": [0, 1, 2] * 3, "cycle4": [0, 1, 2, 3] * 2}[pattern][:n]
+    lat.step_sequence(src, [bufs[j] for j in idx])
+    prev, ref = src, []
+    for _ in range(n):
+        prev = _step(lat, prev)
+        ref.append(prev)
+    for j in set(idx):
+        last = max(i for i, jj in enumerate(idx) if jj == j)
+        assert torch.equal(bufs[j], ref[last]), (j, last)
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("T", [0, 1, 10, 23])
 def test_rollout_gradient_independent_of_checkpointing(storage, T):
