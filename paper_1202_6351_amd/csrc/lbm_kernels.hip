@@ -294,17 +294,28 @@ __device__ __forceinline__ void store_kept(const Geom& g, S* __restrict__ dst, i
 
 // Stores of one node's nine post-collision values as the storage type, with
 // the step's rounding: nearest even, or stochastic with 16 random bits per
-// population from a chain of PCG hashes keyed by the node and the step.
+// population.  The bits of populations 0 and 1 are the PCG hash of the node
+// and the step's key; those of populations 2..8 come from Marsaglia's
+// xorshift32 (shifts 13, 17, 5; "Xorshift RNGs", J. Stat. Softw. 2003)
+// seeded from that hash with its low bit set (xorshift32 never leaves 0).
+// Each of its states is uniform over the non-zero 32-bit words, so every
+// population's rounding stays unbiased, without the integer multiplies of
+// a hash per pair.
 template <typename S, bool SR>
 __device__ __forceinline__ void round_out(const typename Codec<S>::R out[9], uint32_t node, uint32_t key,
                                           S o[9]) {
   if constexpr (SR) {
-    uint32_t h = pcg_hash(node ^ key);
+    const uint32_t h = pcg_hash(node ^ key);
+    o[0] = Codec<S>::store_sr(out[0], h >> 16);
+    o[1] = Codec<S>::store_sr(out[1], h);
+    uint32_t x = (h ^ 0x9E3779B9u) | 1u;
 #pragma unroll
-    for (int k = 0; k < 9; k += 2) {
-      o[k] = Codec<S>::store_sr(out[k], h >> 16);
-      if (k + 1 < 9) o[k + 1] = Codec<S>::store_sr(out[k + 1], h);
-      h = pcg_hash(h);
+    for (int k = 2; k < 9; k += 2) {
+      x ^= x << 13;
+      x ^= x >> 17;
+      x ^= x << 5;
+      o[k] = Codec<S>::store_sr(out[k], x >> 16);
+      if (k + 1 < 9) o[k + 1] = Codec<S>::store_sr(out[k + 1], x);
     }
   } else {
 #pragma unroll
