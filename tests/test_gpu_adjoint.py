@@ -330,6 +330,40 @@ def test_sequences_equal_single_calls(storage, n, bci, shape):
     assert torch.equal(gf_a, gf_b)
 
 
+def test_handle_on_another_stream():
+    """Lattice.on_stream: a context of its own over the same buffers, whose
+    calls run on the given stream.  Its kept states equal the original's; it
+    has no state of its own (state calls fail with LBM_ESTATE); making many
+    of them allocates no device memory (the diagnostics scratch is made on
+    first use)."""
+    from paper_1202_6351_amd import _lib
+    nx, ny = 130, 70
+    bc, wu = BCS[1]
+    lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=16), storage="fp32", tau=0.7, bc=bc, wall_u=wu)
+    lat.set_populations(W.random_populations(nx, ny, seed=17, amp=0.05))
+    src = lat.snapshot()
+    ref = [lat.new_lattice() for _ in range(5)]
+    lat.step_sequence(src, ref)
+    side = torch.cuda.Stream()
+    v = lat.on_stream(side)
+    got = [lat.new_lattice() for _ in range(5)]
+    torch.cuda.current_stream().synchronize()
+    with torch.cuda.stream(side):
+        v.step_sequence(src, got)
+    side.synchronize()
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    with pytest.raises(_lib.LbmError) as e:
+        v.step(1)
+    assert e.value.status == _lib.LBM_ESTATE
+    torch.cuda.synchronize()
+    before = torch.cuda.mem_get_info()[0]
+    views = [lat.on_stream(side) for _ in range(50)]
+    assert torch.cuda.mem_get_info()[0] == before
+    del views
+    assert lat.diagnostics()[0] > 0  # the original's first diagnostics call makes its scratch
+
+
 @pytest.mark.parametrize("pattern", ["pingpong", "cycle3", "cycle4"])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_step_sequence_with_reused_buffers(pattern, storage):
