@@ -119,7 +119,9 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
     g.ld_soff[k] = g.fast ? (uint32_t)ld : 0u;
     g.st_soff[k] = g.fast ? (uint32_t)st : 0u;
   }
-  g.t2_ty = storage_size(p->storage) == 8 ? 8 : 16;
+  // 64 x 16 tiles, or 64 x 8 where 64 x 16 would leave the chip short of
+  // workgroups (measured: 16-bit 512^2 49 -> 64 GLUPS, 1024^2 120 -> 135)
+  g.t2_ty = storage_size(p->storage) == 8 || (int64_t)p->nx * p->ny <= lbm::kStep2SmallMaxNodes ? 8 : 16;
   g.t2_tiles_x = (int32_t)((p->nx + 63) / 64);
   g.t2_tiles_y = (int32_t)((p->ny + g.t2_ty - 1) / g.t2_ty);
   if (storage_size(p->storage) != 8) {

@@ -1268,19 +1268,29 @@ static hipError_t launch_step_fm(const KArgs<typename Codec<S>::R>& k, const voi
   return hipGetLastError();
 }
 
-template <typename S, bool SR>
-static hipError_t launch_step2_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                                  uint32_t kb, hipStream_t st) {
+template <typename S, bool SR, int TY>
+static void launch_step2_ty(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                            uint32_t kb, hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(k.g.t2_tiles_x * k.g.t2_tiles_y));
-  constexpr int TY = sizeof(S) == 8 ? 8 : 16;
-  if (k.g.t2_ty != TY) return hipErrorInvalidValue;
   if (fm == 0)
     hipLaunchKernelGGL((k_step2<S, 0, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
   else if (fm == 1)
     hipLaunchKernelGGL((k_step2<S, 1, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
   else
     hipLaunchKernelGGL((k_step2<S, 2, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+}
+
+// Tile height 8 (FP64 always, the other storages on small lattices) or 16.
+template <typename S, bool SR>
+static hipError_t launch_step2_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                  uint32_t kb, hipStream_t st) {
+  if (k.g.t2_ty == 8)
+    launch_step2_ty<S, SR, 8>(k, src, dst, ka, kb, st);
+  else if (sizeof(S) != 8 && k.g.t2_ty == 16)
+    launch_step2_ty<S, SR, sizeof(S) == 8 ? 8 : 16>(k, src, dst, ka, kb, st);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

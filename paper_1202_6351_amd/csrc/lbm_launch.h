@@ -62,6 +62,10 @@ constexpr int64_t kStripMaxNodes = (int64_t)6 << 20;
 // bytes, so that the next launch finds the state in the last-level cache.
 constexpr int64_t kWriteBackMaxBytes = (int64_t)192 << 20;
 
+// Two-step kernel: 64 x 8 tiles (instead of 64 x 16) for lattices of up to
+// this many nodes.
+constexpr int64_t kStep2SmallMaxNodes = (int64_t)1 << 21;
+
 // Two-step adjoint tile heights (64 x TY tiles, 256 threads).
 constexpr int kAdjoint2TyF32 = 8, kAdjoint2TyF64 = 4;
 

@@ -165,6 +165,7 @@ def test_fp32_three_step_kernels_either_side_of_switch(shape, case):
     lat.init_equilibrium(*fields)
     lat.step(30)
     _fused_equals_single(lat, 3)
+    _fused_equals_single(lat, 2)  # the two-step launch of a remainder (64 x 16 tiles here)
     if case != "cavity":
         return
     f_n = lat.populations().cpu().numpy()
