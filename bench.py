@@ -6,16 +6,17 @@ Headline (`value`): MLUPS of the plain FP32 step on the lid-driven cavity
 4096 x 4096 (Re 1000, lid 0.1, tau 1.7288; seeded density noise 1e-6), with
 the lattices resident in HBM: W untimed steps, then exactly K steps (default
 100 000, the study's step count at its largest grid) timed with
-HIP events on the library's stream (lbm_step fuses three steps per launch in
-FP32 and FP64, two in FP16/BF16).  One JSON line on stdout, also carrying:
-  roofline      the dominant kernel (the three-step FP32 launch) against
+HIP events on the library's stream (lbm_step fuses four steps per launch in
+FP64 and in FP32 above 2^20 nodes, three in smaller FP32 lattices, two in
+FP16/BF16).  One JSON line on stdout, also carrying:
+  roofline      the dominant kernel (the four-step FP32 launch) against
                 MI355X's 8 TB/s: its algorithmic bytes per launch -- the
                 method's 72 B per FP32 cell update (nine populations read and
-                nine written) times the three updates of every node -- over
+                nine written) times the four updates of every node -- over
                 its measured average duration (an event between the whole
                 groups and any remainder of K separates the dominant
-                launches).  Fusing three steps moves only a third of those
-                bytes (the state read and written once per launch, 24 B per
+                launches).  Fusing four steps moves only a quarter of those
+                bytes (the state read and written once per launch, 18 B per
                 update), so frac can exceed 1; the bytes actually moved and
                 their rate are reported beside it, and so is the VALU issue
                 rate from the committed SQ_INSTS_VALU count against the
@@ -50,25 +51,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # Algorithmic bytes per cell update (nine populations read, nine written),
 # which is also what one node moves through HBM per launch: a launch reads
-# and writes the state once and advances every node by UPDATES_PER_LAUNCH
-# steps (the library's grouping per storage mode).
+# and writes the state once and advances every node by updates_per_launch
+# steps (the library's grouping).
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}
-UPDATES_PER_LAUNCH = {"fp64": 3, "fp32": 3, "fp16": 2, "bf16": 2}
+STRIP_MAX_NODES = 1 << 20  # FP32 lattices up to this size take the strip kernel
 METRIC = "MLUPS + % HBM peak, FP32 vs FP16-storage; fwd+adjoint MLUPS at fixed error"
 STEP_SOURCES = ["paper_1202_6351_amd/csrc/lbm_kernels.hip", "paper_1202_6351_amd/csrc/cascade.h",
                 "paper_1202_6351_amd/csrc/lbm_launch.h", "paper_1202_6351_amd/csrc/lbm_api.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step3_fp32_cavity4096.txt")
-VALU_FILE = os.path.join(ROOT, "profiles", "valu_step3_fp32_cavity4096.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step4_fp32_cavity4096.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_step4_fp32_cavity4096.txt")
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed lane
 # instructions per second).
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# One FP32 collision without body force in the kernels' factorised form: 100
+# VALU operations (31 add, 17 sub, 13 mul, 38 fma, 1 rcp), 138 flops with an
+# fma counted as two.
+COLLISION_OPS_FP32, COLLISION_FLOPS_FP32 = 100, 138
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # published, packed FP32 FMA
 
 
-def three_step_kernel(n: int) -> str:
-    """The kernel the library runs for an n x n FP32 lattice's three-step
-    launches: strips up to 6 Mi nodes, 64 x TY tiles above."""
-    name = "k_strip<float>" if n * n <= 6 * (1 << 20) else "k_step3<float>"
-    return f"{name} (three steps per launch)"
+def updates_per_launch(storage: str, nodes: int) -> int:
+    """Steps the library fuses per launch: four on the 64 x TY tiles (FP64,
+    FP32 above STRIP_MAX_NODES), three on the FP32 strips, two in 16-bit."""
+    if storage in ("fp16", "bf16"):
+        return 2
+    return 3 if storage == "fp32" and nodes <= STRIP_MAX_NODES else 4
+
+
+def fp32_kernel(n: int) -> str:
+    """The kernel of an n x n FP32 lattice's fused launches."""
+    if updates_per_launch("fp32", n * n) == 3:
+        return "k_strip<float> (three steps per launch)"
+    return "k_step4<float> (four steps per launch)"
 
 
 def kernel_hash() -> str:
@@ -261,7 +275,7 @@ def main():
         rounding = args.rounding if args.only != "fp64" else "nearest"
         lat = (taylor_green_lattice(n, args.only, rounding=rounding) if args.only != "fp64"
                else cavity_lattice(n, "fp64")[0])
-        grp = UPDATES_PER_LAUNCH[args.only]
+        grp = updates_per_launch(args.only, n * n)
         dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
         mlups = n * n * args.steps / dt / 1e6
         gbs = BYTES_PER_NODE[args.only] * n * n * launches / dt_main / 1e9 if launches else None
@@ -272,7 +286,7 @@ def main():
 
     n = args.n
     lat, tau = cavity_lattice(n, "fp32")
-    grp = UPDATES_PER_LAUNCH["fp32"]
+    grp = updates_per_launch("fp32", n * n)
     if args.steps < grp:
         raise SystemExit(f"--steps must be at least {grp} (one fused launch)")
     dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
@@ -293,7 +307,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": three_step_kernel(n),
+                     "kernel": fp32_kernel(n),
                      "launch_us": round(per_launch * 1e6, 2),
                      "updates_per_launch": grp,
                      "alg_bytes_per_update": BYTES_PER_NODE["fp32"],
@@ -304,10 +318,17 @@ def main():
                          "achieved_tops": round(valu * 64 / per_launch / 1e12, 2),
                          "peak_tops": round(VALU_PEAK_LANE_OPS / 1e12, 2),
                          "frac": round(valu * 64 / per_launch / VALU_PEAK_LANE_OPS, 4)},
-                     "note": "three steps per launch: the state crosses HBM once per three updates, "
-                             "so the algorithmic rate exceeds the single-pass HBM roofline; the launch "
-                             "is bound by HBM (it moves its 24 B per update at about 90 % of the rate a "
-                             "plain copy reaches on this GPU, 5.07 TB/s), VALU issue second (valu)"},
+                     "collision": {
+                         "ops_per_update": COLLISION_OPS_FP32, "flops_per_update": COLLISION_FLOPS_FP32,
+                         "ops_frac": round(COLLISION_OPS_FP32 * grp * n * n / per_launch / VALU_PEAK_LANE_OPS, 4),
+                         "achieved_tflops": round(COLLISION_FLOPS_FP32 * grp * n * n / per_launch / 1e12, 2),
+                         "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_TFLOPS},
+                     "note": f"{grp} steps per launch: the state crosses HBM once per {grp} updates, "
+                             "so the algorithmic rate exceeds the single-pass HBM roofline.  The launch "
+                             "is bound by VALU issue (valu.frac of 256 CUs x 64 lanes x 2.4 GHz; the "
+                             "collision's own operations are collision.ops_frac of it, the rest is the "
+                             "recompute ring and staging); its moved bytes run at moved_frac of HBM "
+                             "peak (a plain copy reaches 5.07 TB/s)"},
         "mass_drift_rel": float(f"{abs(d[0] / (n * n) - 1.0):.2e}"),
     }
     del lat
@@ -317,7 +338,7 @@ def main():
         sizes = {}
         for ns, re in ((1024, 1000.0), (2048, 1000.0), (4096, 5000.0)):
             ls, _ = cavity_lattice(ns, "fp32", re)
-            dts, _, _ = timed_steps(ls, 2100, 300, grp)
+            dts, _, _ = timed_steps(ls, 2100, 300, updates_per_launch("fp32", ns * ns))
             sizes[f"cavity_{ns}x{ns}_re{int(re)}_fp32"] = round(ns * ns * 2100 / dts / 1e6, 1)
             del ls
             torch.cuda.empty_cache()
@@ -327,7 +348,7 @@ def main():
         for storage in ("fp16", "bf16"):
             for rounding in ("nearest", "stochastic"):
                 l16 = taylor_green_lattice(8192, storage, rounding=rounding)
-                g16 = UPDATES_PER_LAUNCH[storage]
+                g16 = updates_per_launch(storage, 8192 * 8192)
                 steps16 = max(10, min(args.steps // 4, 2000))
                 steps16 -= steps16 % g16
                 dt16, _, launches16 = timed_steps(l16, steps16, max(2, args.warmup // 4), g16)

@@ -19,12 +19,12 @@
 // Launch shape of the single step: 256-thread blocks covering TX x (256/TX)
 // nodes, TX in {64, 128, 256} (a 64-wide wavefront spans one row segment).
 // The fused launches keep intermediate steps in LDS, so the state crosses
-// HBM once per two or three steps.  k_step2 and k_step3 give each workgroup
-// a 64 x TY tile plus a recompute ring (two or three steps); k_strip gives it
-// a strip of 60 columns that it walks down row by row, one wavefront per row
-// and step, the intermediate rows in small LDS rings, so that only the strip's
-// sides are recomputed (three steps, FP32 lattices up to 6 Mi nodes, where
-// it leads).  In every kernel the 1-D block index is remapped so that each of
+// HBM once per two, three or four steps.  k_step2, k_step3 and k_step4 give
+// each workgroup a 64 x TY tile plus a recompute ring (two, three or four
+// steps); k_strip gives it a strip of 60 columns that it walks down row by
+// row, one wavefront per row and step, the intermediate rows in small LDS
+// rings, so that only the strip's sides are recomputed (three steps, FP32
+// lattices up to 1 Mi nodes, where it leads).  In every kernel the 1-D block index is remapped so that each of
 // the 8 XCDs (blocks are dealt to XCDs round-robin) processes one contiguous
 // band of tiles, keeping the lines shared between horizontally and
 // vertically adjacent tiles in one L2.
@@ -633,6 +633,40 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
   } else {
     stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
     stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_c, mid, dst);
+  }
+}
+
+// Four fused steps per launch (FP32 above 1 Mi nodes, FP64 at every size).
+// Step n on the tile plus a three-node ring (70 x (TY+6)) from HBM into LDS;
+// steps n+1 and n+2 in place in LDS on the tile plus a two- and a one-node
+// ring; step n+3 on the tile to HBM.  HBM traffic per update is a quarter of
+// a single step's; the rings cost
+// (70 (TY+6) + 68 (TY+4) + 66 (TY+2) + 64 TY) / (4 * 64 TY) - 1 extra
+// collisions: 18 % at TY = 24 (FP32, 74 KB of LDS) and 45 % at TY = 8 (FP64,
+// 69 KB), two 512-thread workgroups per CU in both.
+template <typename S, int FM, bool SR, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
+                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
+                                               uint32_t key_c, uint32_t key_d) {
+  // 768-thread workgroups gave wrong results on the rows next to a periodic
+  // y boundary (cause not found; 256 and 512 threads are exact).
+  static_assert((NT & (NT - 1)) == 0, "power-of-two workgroups only");
+  constexpr int H = 3, EW = 64 + 2 * H, EH = TY + 2 * H;
+  __shared__ S mid[9][EH][EW];
+  const auto rt = rates(a);
+  int x0, y0;
+  bool interior, fast;
+  tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
+  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  __syncthreads();
+  if (interior) {  // workgroup-uniform: every thread meets the same barriers
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 2, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_c, mid);
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_d, mid, dst);
+  } else {
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 2, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_c, mid);
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_d, mid, dst);
   }
 }
 
@@ -1368,6 +1402,34 @@ hipError_t launch_strip3(const KArgsAny& a, const void* src, void* dst, uint32_t
                          uint32_t key_c, hipStream_t st) {
   if (a.storage != 1) return hipErrorInvalidValue;
   return launch_strip3_fm<false, false>(a.f, src, dst, nullptr, nullptr, key_a, key_b, key_c, st);
+}
+
+template <typename S, int TY, int NT>
+static hipError_t launch_step4_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                  uint32_t kb, uint32_t kc, uint32_t kd, hipStream_t st) {
+  const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
+  const dim3 grid((unsigned)(k.g.t3_tiles_x * ((k.g.ny + TY - 1) / TY)));
+  if (fm == 0)
+    hipLaunchKernelGGL((k_step4<S, 0, false, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc,
+                       kd);
+  else if (fm == 1)
+    hipLaunchKernelGGL((k_step4<S, 1, false, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc,
+                       kd);
+  else
+    hipLaunchKernelGGL((k_step4<S, 2, false, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc,
+                       kd);
+  return hipGetLastError();
+}
+
+hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                        uint32_t key_c, uint32_t key_d, hipStream_t st) {
+  switch (a.storage) {
+    case 0:
+      return launch_step4_fm<double, kStep4TyF64, kStep4ThreadsF64>(a.d, src, dst, key_a, key_b, key_c, key_d, st);
+    case 1:
+      return launch_step4_fm<float, kStep4TyF32, kStep4ThreadsF32>(a.f, src, dst, key_a, key_b, key_c, key_d, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_strip3_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* dst,

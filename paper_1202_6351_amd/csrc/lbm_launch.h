@@ -50,17 +50,22 @@ constexpr int64_t kStep3LargeMinNodes = 1 << 20;
 // kStripRounds waves of resident workgroups (segments per strip =
 // kStripRounds x resident workgroups / strips), segments at least
 // kStripMinLen rows.  FP32 lattices of up to kStripMaxNodes nodes take the
-// strip kernel; larger ones, and FP64, the 64 x TY tiles (measured on one
-// MI355X: strips lead up to 2048^2, tiles from 2896^2 up, and for FP64 at
-// every size).
+// strip kernel; larger ones, and FP64, the four-step 64 x TY tiles
+// (measured on one MI355X: the four-step tiles lead from 1024^2 up, by 10 %
+// at 2048^2 and 12 % at 4096^2).
 constexpr int kStripWaves = 4, kStripRing = 6;
 constexpr int kStripRounds = 16, kStripMinLen = 8;
-constexpr int64_t kStripMaxNodes = (int64_t)6 << 20;
+constexpr int64_t kStripMaxNodes = (int64_t)1 << 20;
 
 // Step kernels write a lattice back through the caches (instead of
 // streaming it past them) when both lattices together take at most this many
 // bytes, so that the next launch finds the state in the last-level cache.
 constexpr int64_t kWriteBackMaxBytes = (int64_t)192 << 20;
+
+// Four-step kernel: 64 x TY tiles, NT threads per workgroup (two workgroups
+// per CU in both precisions).
+constexpr int kStep4TyF32 = 24, kStep4ThreadsF32 = 512;
+constexpr int kStep4TyF64 = 8, kStep4ThreadsF64 = 512;
 
 // Two-step kernel: 64 x 8 tiles (instead of 64 x 16) for lattices of up to
 // this many nodes.
@@ -120,6 +125,10 @@ hipError_t launch_strip3_keep(const KArgsAny& a, const void* src, void* keep0, v
 // Workgroups of the three-step strip kernel resident on the current device at
 // once (compute units x workgroups per unit); 0 if the device query fails.
 int strip3_resident();
+// Four steps in one launch (FP32, FP64): src (state n) -> dst (state n+4), keys of
+// steps n .. n+3.  Same result as four launch_step calls.
+hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
+                        uint32_t key_c, uint32_t key_d, hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);

@@ -116,12 +116,14 @@ def _fused_equals_single(lat, group):
     assert torch.equal(fused, lat.current)
 
 
-@pytest.mark.parametrize("storage,tol", [("fp32", 4e-7), ("fp64", 6e-15)])
-def test_cavity_4096_three_step_launch(storage, tol):
-    """The benchmark's launch: FP32 (and FP64) cavity 4096^2, Re 1000, three
-    steps in one launch after 300 warm-up steps.  Bit-exact against three
-    single steps; at sampled nodes within tol of three FP64 oracle steps from
-    the same read-back state (FP32: three steps of FP32 rounding)."""
+@pytest.mark.parametrize("storage,group,tol", [("fp32", 4, 4e-7), ("fp32", 3, 4e-7), ("fp64", 4, 6e-15),
+                                               ("fp64", 3, 6e-15)])
+def test_cavity_4096_fused_launch(storage, group, tol):
+    """The benchmark's launch: cavity 4096^2, Re 1000, four steps in one
+    launch after 300 warm-up steps, and the three-step launch of a
+    remainder.  Bit-exact against single steps; at sampled nodes within tol
+    of as many FP64 oracle steps from the same read-back state (FP32: the
+    steps' FP32 rounding)."""
     from paper_1202_6351_amd import Lattice, Params
     n = 4096
     tau = W.cavity_tau(n, 0.1, 1000.0)
@@ -129,28 +131,30 @@ def test_cavity_4096_three_step_launch(storage, tol):
                   device="cuda:0")
     lat.init_equilibrium(*W.at_rest(n, n, density_noise=1e-6, seed=2))
     lat.step(300)
-    _fused_equals_single(lat, 3)
+    _fused_equals_single(lat, group)
     f_n = lat.populations().cpu().numpy()
-    lat.step(3)
+    lat.step(group)
     p = oracle.Params(n, n, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
-    want_all = oracle.step(p, f_n, 3)
+    want_all = oracle.step(p, f_n, group)
     del f_n
     xs, ys = _sample_nodes(n, n, 3000, seed=5)
     got = lat.populations()[:, torch.from_numpy(ys).long().cuda(), torch.from_numpy(xs).long().cuda()].cpu().numpy()
     want = want_all[:, ys, xs]
     err = np.abs(got - want)
-    print(f"{storage} 4096x4096: max three-step error {err.max():.3e} over {len(xs)} nodes")
+    print(f"{storage} 4096x4096: max {group}-step error {err.max():.3e} over {len(xs)} nodes")
     assert err.max() <= tol
 
 
-@pytest.mark.parametrize("shape", [(2500, 2515), (2600, 2597)])
+@pytest.mark.parametrize("shape", [(1000, 1045), (1024, 1024), (1021, 1031), (2600, 2597)])
 @pytest.mark.parametrize("case", ["cavity", "periodic_force"])
-def test_fp32_three_step_kernels_either_side_of_switch(shape, case):
-    """FP32 three-step launches take the strip kernel up to 6 Mi nodes and the
-    64 x TY tiles above: 2500 x 2515 (6287500 nodes) and 2600 x 2597
-    (6752200), both ragged in x and y, each bit-exact against three single
-    steps; the cavity case also within 4e-7 of three FP64 oracle steps at
-    sampled nodes."""
+def test_fp32_fused_kernels_either_side_of_switch(shape, case):
+    """FP32 lattices of up to 2^20 nodes fuse three steps per launch in the
+    strip kernel, larger ones four in the 64 x TY tiles: 1000 x 1045 (ragged)
+    and 1024 x 1024 (the largest strip lattice) below, 1021 x 1031 and
+    2600 x 2597 (ragged in x and y) above.  Four-, three- and two-step
+    launches each bit-exact against single steps; the cavity case also within
+    4e-7 of as many FP64 oracle steps as the main launch fuses, at sampled
+    nodes."""
     from paper_1202_6351_amd import Lattice, Params
     nx, ny = shape
     if case == "cavity":
@@ -164,19 +168,21 @@ def test_fp32_three_step_kernels_either_side_of_switch(shape, case):
     lat = Lattice(Params(nx, ny, tau=tau, storage="fp32", **kw), device="cuda:0")
     lat.init_equilibrium(*fields)
     lat.step(30)
+    _fused_equals_single(lat, 4)  # above the switch: the four-step tile launch
     _fused_equals_single(lat, 3)
-    _fused_equals_single(lat, 2)  # the two-step launch of a remainder (64 x 16 tiles here)
+    _fused_equals_single(lat, 2)  # the two-step launch of a remainder
     if case != "cavity":
         return
+    group = 3 if nx * ny <= (1 << 20) else 4
     f_n = lat.populations().cpu().numpy()
-    lat.step(3)
+    lat.step(group)
     p = oracle.Params(nx, ny, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
-    want_all = oracle.step(p, f_n, 3)
+    want_all = oracle.step(p, f_n, group)
     del f_n
     xs, ys = _sample_nodes(nx, ny, 2000, seed=7)
     got = lat.populations()[:, torch.from_numpy(ys).long().cuda(), torch.from_numpy(xs).long().cuda()].cpu().numpy()
     err = np.abs(got - want_all[:, ys, xs])
-    print(f"fp32 {nx}x{ny}: max three-step error {err.max():.3e} over {len(xs)} nodes")
+    print(f"fp32 {nx}x{ny}: max {group}-step error {err.max():.3e} over {len(xs)} nodes")
     assert err.max() <= 4e-7
 
 
