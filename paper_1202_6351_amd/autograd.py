@@ -11,12 +11,15 @@ through each step in reverse (transposed per-node Jacobian of the cascaded
 collision and forcing, then reverse streaming), then through the
 initial-state map.
 
-Memory: the forward keeps a lattice snapshot every `checkpoint_every` steps.
-The backward recomputes each segment's states from its snapshot and runs the
-adjoint over them newest-first.  The recompute of the next (older) segment
-runs on one stream while the adjoint of the current one runs on another, so
-the two kernels share the GPU; they alternate between two sets of
-`checkpoint_every - 1` lattice buffers.  Both streams are ordinary streams
+Memory: the forward keeps a lattice snapshot every `checkpoint_every` steps,
+and, when a gradient is wanted, every state of the last segment (it runs
+that segment as one state-keeping sequence, so the backward can start its
+adjoint at once).  The backward recomputes each older segment's states from
+its snapshot and runs the adjoint over them newest-first.  The recompute of
+the next (older) segment runs on one stream while the adjoint of the current
+one runs on another, so the two kernels share the GPU; they alternate
+between two sets of `checkpoint_every` lattice buffers (the forward's set and
+one more), each set one allocation.  Both streams are ordinary streams
 kept per device (not the legacy default stream, whose implicit
 synchronisation with other streams serialised the two).  Work per step of
 the backward: one recomputed step and one adjoint step.
@@ -31,6 +34,16 @@ from .lattice import Lattice, Params
 
 
 _BACKWARD_STREAMS = {}
+
+
+def _lattice_set(lat: Lattice, count: int):
+    """(base tensor, list of `count` lattice buffers): views of one
+    allocation, each at a multiple of the lattice size (a multiple of 256
+    bytes, since the pitch is a multiple of 64 nodes)."""
+    if count <= 0:
+        return None, []
+    base = torch.empty((count, lat.lat[0].numel()), dtype=lat.lat[0].dtype, device=lat.device)
+    return base, [base[i] for i in range(count)]
 
 
 def _backward_streams(dev: torch.device):
@@ -59,19 +72,26 @@ class Rollout(torch.autograd.Function):
         ux0 = u0[0].detach().to(dtype=f64).contiguous()
         uy0 = u0[1].detach().to(dtype=f64).contiguous()
         lat.init_equilibrium(rho, ux0, uy0)
-        snaps = []
-        t = 0
-        while True:
-            snaps.append(lat.snapshot())
-            n = min(every, steps - t)
+        nseg = max(1, -(-steps // every))
+        snap_base, snaps = _lattice_set(lat, nseg)
+        keep_base, keep = None, []
+        for s in range(nseg):
+            lat.snapshot(snaps[s])
+            n = min(every, steps - s * every)
             if n <= 0:
                 break
-            lat.step(n)
-            t += n
-            if t >= steps:
-                break
+            if s == nseg - 1 and any(ctx.needs_input_grad[:2]):
+                # the last segment keeps its states for the backward; its
+                # final state becomes the lattice's current state
+                keep_base, keep = _lattice_set(lat, every)
+                lat.step_sequence(snaps[s], keep[:n])
+                lat.restore(keep[n - 1], steps)
+            else:
+                lat.step(n)
         m = lat.macroscopic(strain=False)
         ctx.lat, ctx.snaps, ctx.steps, ctx.every = lat, snaps, steps, every
+        ctx.bases = (snap_base, keep_base)
+        ctx.keep = keep
         ctx.init_fields = (rho, ux0, uy0)
         return m["rho"], torch.stack([m["ux"], m["uy"]])
 
@@ -90,7 +110,9 @@ class Rollout(torch.autograd.Function):
         nseg = len(snaps)
         seg_len = [max(min(every, steps - s * every), 0) for s in range(nseg)]
         width = max(min(every, max(steps, 0)) - 1, 0)
-        sets = [[torch.empty_like(lat.lat[0]) for _ in range(width)] for _ in range(2)]
+        # set 0: the forward's kept states of the last segment; set 1: new
+        set1_base, set1 = _lattice_set(lat, width if nseg > 1 else 0)
+        sets = [ctx.keep, set1]
         rho, ux0, uy0 = ctx.init_fields
         g_ux0 = torch.empty_like(ux0, dtype=real)
         g_uy0 = torch.empty_like(uy0, dtype=real)
@@ -106,7 +128,7 @@ class Rollout(torch.autograd.Function):
         for st in (main, side):
             st.wait_stream(lat.stream)
             st.wait_stream(caller)
-        for t in (*snaps, *sets[0], *sets[1], lat.force, lat.current, grad_force, mu, mu2, g_rho, g_ux, g_uy,
+        for t in (*ctx.bases, set1_base, lat.force, lat.current, grad_force, mu, mu2, g_rho, g_ux, g_uy,
                   g_ux0, g_uy0, rho, ux0, uy0):
             if t is not None:
                 t.record_stream(side)
@@ -125,13 +147,14 @@ class Rollout(torch.autograd.Function):
                 rec.step_sequence(snaps[s], sets[b][:max(seg_len[s] - 1, 0)])
                 ready[b].record(side)
 
-        recompute(nseg - 1, 0)
+        # the last segment's states were kept by the forward
         with torch.cuda.stream(main):
             for k, s in enumerate(range(nseg - 1, -1, -1)):
                 b = k % 2
                 if s > 0:
                     recompute(s - 1, 1 - b)
-                main.wait_event(ready[b])
+                if k > 0:  # set 0 of the first segment: ordered by the forward's stream
+                    main.wait_event(ready[b])
                 n = seg_len[s]
                 states = [snaps[s]] + sets[b][:max(n - 1, 0)]
                 if s == nseg - 1:
@@ -143,7 +166,7 @@ class Rollout(torch.autograd.Function):
             main.wait_stream(side)
             adj.adjoint_init(rho, ux0, uy0, mu, None, g_ux0, g_uy0, grad_force)
         caller.wait_stream(main)
-        ctx.lat = ctx.snaps = None
+        ctx.lat = ctx.snaps = ctx.keep = ctx.bases = None
         return grad_force, torch.stack([g_ux0, g_uy0]), None, None, None, None
 
 

@@ -417,6 +417,24 @@ def test_rollout_gradient_independent_of_checkpointing(storage, T):
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("T,every", [(23, 10), (20, 10), (5, 40)])
+def test_rollout_forward_same_with_and_without_gradient(storage, T, every):
+    """With a gradient wanted, the forward runs its last segment as a
+    state-keeping sequence and restores the final state; the outputs equal
+    those of the plain stepping forward bit for bit."""
+    from paper_1202_6351_amd import Params, rollout
+    nx, ny = 40, 24
+    bc, wu = BCS[1]
+    p = Params(nx, ny, tau=0.7, bc=bc, wall_u=wu, storage=storage)
+    real = p.real_dtype
+    F = torch.from_numpy(W.force_field(nx, ny, 1e-4, seed=9)).to(DEV, real)
+    u0 = torch.from_numpy(np.stack(W.random_flow(nx, ny, seed=5, u_amp=0.03)[1:])).to(DEV, real)
+    rho_a, u_a = rollout(p, F, u0, T, checkpoint_every=every)
+    rho_b, u_b = rollout(p, F.clone().requires_grad_(True), u0, T, checkpoint_every=every)
+    assert torch.equal(rho_a, rho_b) and torch.equal(u_a, u_b.detach())
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
 def test_step_sequence_large_shape(storage):
     """lbm_step_sequence on 1030 x 1030 (FP64 takes its large three-step
     shape there), walls and lid, force field: seven kept states equal seven
