@@ -7,8 +7,7 @@ Headline (`value`): MLUPS of the plain FP32 step on the lid-driven cavity
 the lattices resident in HBM: W untimed steps, then exactly K steps (default
 100 000, the study's step count at its largest grid) timed with
 HIP events on the library's stream (lbm_step fuses four steps per launch in
-FP64 and in FP32 above 2^20 nodes, three in smaller FP32 lattices, two in
-FP16/BF16).  One JSON line on stdout, also carrying:
+FP64 and FP32, two in FP16/BF16).  One JSON line on stdout, also carrying:
   roofline      the dominant kernel (the four-step FP32 launch) against
                 MI355X's 8 TB/s: its algorithmic bytes per launch -- the
                 method's 72 B per FP32 cell update (nine populations read and
@@ -54,7 +53,6 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # and writes the state once and advances every node by updates_per_launch
 # steps (the library's grouping).
 BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}
-STRIP_MAX_NODES = 1 << 20  # FP32 lattices up to this size take the strip kernel
 METRIC = "MLUPS + % HBM peak, FP32 vs FP16-storage; fwd+adjoint MLUPS at fixed error"
 STEP_SOURCES = ["paper_1202_6351_amd/csrc/lbm_kernels.hip", "paper_1202_6351_amd/csrc/cascade.h",
                 "paper_1202_6351_amd/csrc/lbm_launch.h", "paper_1202_6351_amd/csrc/lbm_api.hip"]
@@ -71,17 +69,13 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # published, packed FP32 FMA
 
 
 def updates_per_launch(storage: str, nodes: int) -> int:
-    """Steps the library fuses per launch: four on the 64 x TY tiles (FP64,
-    FP32 above STRIP_MAX_NODES), three on the FP32 strips, two in 16-bit."""
-    if storage in ("fp16", "bf16"):
-        return 2
-    return 3 if storage == "fp32" and nodes <= STRIP_MAX_NODES else 4
+    """Steps the library fuses per launch: four on the 64 x TY tiles in FP64
+    and FP32, two in 16-bit storage."""
+    return 2 if storage in ("fp16", "bf16") else 4
 
 
 def fp32_kernel(n: int) -> str:
     """The kernel of an n x n FP32 lattice's fused launches."""
-    if updates_per_launch("fp32", n * n) == 3:
-        return "k_strip<float> (three steps per launch)"
     return "k_step4<float> (four steps per launch)"
 
 
@@ -253,8 +247,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
-    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64"], default=None,
-                    help="time one storage mode only (profiling runs)")
+    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout"], default=None,
+                    help="time one storage mode, or the forward + adjoint rollout, only (profiling runs)")
     ap.add_argument("--rounding", choices=["nearest", "stochastic"], default="nearest",
                     help="16-bit rounding of an --only fp16/bf16 run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -269,6 +263,9 @@ def main():
     import torch
     if args.copy_calibration:
         copy_calibration()
+    if args.only == "rollout":
+        print(json.dumps({"only": "rollout", **adjoint_rollout()}))
+        return
 
     if args.only in ("fp16", "bf16", "fp64"):
         n = 8192 if args.only != "fp64" else 4096

@@ -181,10 +181,9 @@ lbm_status lbm_get_populations(lbm_ctx* ctx, void* f);
  * central moments about u, relaxation of each central moment at its own
  * rate with central-moment forcing, back to populations; pull streaming with
  * the boundary rules).  Steps are fused per kernel launch, four at a time
- * for LBM_FP64 and for LBM_FP32 above 2^20 nodes, three for smaller LBM_FP32
- * lattices and two for the 16-bit modes, with the intermediate states in
- * on-chip memory; the result equals n single steps bit for bit.  Ping-pong
- * between lat0 and lat1. */
+ * for LBM_FP64 and LBM_FP32 and two for the 16-bit modes, with the
+ * intermediate states in on-chip memory; the result equals n single steps
+ * bit for bit.  Ping-pong between lat0 and lat1. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* One step from lattice buffer src (state n) into dst (state n+1), outside

@@ -24,7 +24,7 @@ struct lbm_ctx {
   double* diag_scratch;  // device: partial sums (diag_blocks * 4) + result (4); first diagnostics call
   int diag_blocks;
   int64_t pitch, lattice_bytes;
-  bool strip3;        // three-step launches take the strip kernel (else 64 x TY tiles)
+  bool strip3;        // state-keeping sequences take the three-step strip kernel
   char err[512];
 };
 
@@ -162,12 +162,9 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
 // Steps fused per launch: three for FP32 and FP64, whose two-step launch
 // leaves VALU idle while HBM streams; two for the 16-bit modes, whose
 // two-step launch already keeps VALU busy.
-// Steps fused per launch: four on the 64 x TY tiles (FP64, FP32 above
-// kStripMaxNodes), three on the FP32 strips, two in 16-bit storage.
-int steps_per_launch(int32_t storage, bool strip3) {
-  if (storage == LBM_FP32 || storage == LBM_FP64) return strip3 ? 3 : 4;
-  return 2;
-}
+// Steps fused per launch: four on the 64 x TY tiles in FP64 and FP32, two in
+// 16-bit storage.
+int steps_per_launch(int32_t storage) { return (storage == LBM_FP32 || storage == LBM_FP64) ? 4 : 2; }
 
 bool aligned(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
 
@@ -316,7 +313,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   // Steps run in groups of steps_per_launch fused in one launch
   // (intermediate states stay in LDS); the remainder runs as a three-step,
   // a two-step and/or a single-step launch.
-  const int group = steps_per_launch(c->p.storage, c->strip3);
+  const int group = steps_per_launch(c->p.storage);
   int64_t left = n;
   for (; group == 4 && left >= 4; left -= 4) {
     lbm_status s = dev_err(c, lbm::launch_step4(c->args, c->lat[c->cur], c->lat[c->cur ^ 1], step_key(c->p, c->t),
@@ -328,9 +325,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     c->t += 4;
   }
   for (; group >= 3 && left >= 3; left -= 3) {
-    const auto launch3 = c->strip3 ? lbm::launch_strip3 : lbm::launch_step3;
-    lbm_status s = dev_err(c, launch3(c->args, c->lat[c->cur], c->lat[c->cur ^ 1], step_key(c->p, c->t),
-                                      step_key(c->p, c->t + 1), step_key(c->p, c->t + 2), c->stream),
+    lbm_status s = dev_err(c, lbm::launch_step3(c->args, c->lat[c->cur], c->lat[c->cur ^ 1], step_key(c->p, c->t),
+                                                step_key(c->p, c->t + 1), step_key(c->p, c->t + 2), c->stream),
                            "three-step kernel");
     if (s != LBM_OK) return s;
     c->cur ^= 1;

@@ -23,8 +23,9 @@
 // each workgroup a 64 x TY tile plus a recompute ring (two, three or four
 // steps); k_strip gives it a strip of 60 columns that it walks down row by
 // row, one wavefront per row and step, the intermediate rows in small LDS
-// rings, so that only the strip's sides are recomputed (three steps, FP32
-// lattices up to 1 Mi nodes, where it leads).  In every kernel the 1-D block index is remapped so that each of
+// rings, so that only the strip's sides are recomputed (three steps that
+// also store both intermediate states: the state-keeping recompute of FP32
+// lattices up to 1 Mi nodes).  In every kernel the 1-D block index is remapped so that each of
 // the 8 XCDs (blocks are dealt to XCDs round-robin) processes one contiguous
 // band of tiles, keeping the lines shared between horizontally and
 // vertically adjacent tiles in one L2.
@@ -373,18 +374,24 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, con
 
 // Global node of window cell (wx, wy) in unwrapped coordinates: false if it
 // lies beyond a wall, else its wrapped position.
+// gx and gy are assigned on every path, the false one included, and callers
+// call it whether or not they will use the cell: with an output left
+// unassigned on some path, the compiler (ROCm 7.2, gfx950) has zeroed gx for
+// all lanes of the y-wrap branch, the lanes that wrapped among them, when the
+// results went into per-thread arrays of three cells.
 __device__ __forceinline__ bool window_node(const Geom& g, int wx, int wy, int& gx, int& gy) {
+  bool ok = true;
   if (wx < 0 || wx >= g.nx) {
-    if (g.wall[wx < 0 ? 0 : 1]) return false;
+    ok = g.wall[wx < 0 ? 0 : 1] == 0;
     wx = ((wx % g.nx) + g.nx) % g.nx;
   }
   if (wy < 0 || wy >= g.ny) {
-    if (g.wall[wy < 0 ? 2 : 3]) return false;
+    ok = ok & (g.wall[wy < 0 ? 2 : 3] == 0);
     wy = ((wy % g.ny) + g.ny) % g.ny;
   }
   gx = wx;
   gy = wy;
-  return true;
+  return ok;
 }
 
 // The nine populations streaming into node (gx, gy), held in window cell
@@ -499,7 +506,8 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int i = (int)threadIdx.x + NT * j;
-    live[j] = i < EW * EH && window_node(a.g, wx0 + i % EW, wy0 + i / EW, gx[j], gy[j]);
+    const bool in = window_node(a.g, wx0 + i % EW, wy0 + i / EW, gx[j], gy[j]);
+    live[j] = i < EW * EH && in;
     if (live[j]) pull_hbm<S>(a, rs, src, fast, gx[j], gy[j], d[j]);
   }
 #pragma unroll
@@ -642,15 +650,12 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
 // ring; step n+3 on the tile to HBM.  HBM traffic per update is a quarter of
 // a single step's; the rings cost
 // (70 (TY+6) + 68 (TY+4) + 66 (TY+2) + 64 TY) / (4 * 64 TY) - 1 extra
-// collisions: 18 % at TY = 24 (FP32, 74 KB of LDS) and 45 % at TY = 8 (FP64,
-// 69 KB), two 512-thread workgroups per CU in both.
+// collisions: 18 % at TY = 24 (FP32, 74 KB of LDS, 768 threads) and 45 % at
+// TY = 8 (FP64, 69 KB, 512 threads), two workgroups per CU in both.
 template <typename S, int FM, bool SR, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
                                                S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
                                                uint32_t key_c, uint32_t key_d) {
-  // 768-thread workgroups gave wrong results on the rows next to a periodic
-  // y boundary (cause not found; 256 and 512 threads are exact).
-  static_assert((NT & (NT - 1)) == 0, "power-of-two workgroups only");
   constexpr int H = 3, EW = 64 + 2 * H, EH = TY + 2 * H;
   __shared__ S mid[9][EH][EW];
   const auto rt = rates(a);
@@ -726,8 +731,8 @@ __device__ __forceinline__ bool strip_fetch(const KArgs<typename Codec<S>::R>& a
                                             int it, int ys, int ye, int w, int wx, int& gx, int& gy,
                                             typename Codec<S>::R d[9]) {
   const int r0 = ys - (NS - 1) + it * NW + w;
-  if (r0 >= ye + NS - 1) return false;
-  if (!window_node(a.g, wx, r0, gx, gy)) return false;
+  const bool in = window_node(a.g, wx, r0, gx, gy);
+  if (r0 >= ye + NS - 1 || !in) return false;
   gather<S>(a.g, a.wadd, src, gx, gy, d);
   return true;
 }
@@ -1396,12 +1401,6 @@ static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void*
     hipLaunchKernelGGL((k_strip<S, 2, SR, 3, NW, RING, KEEP>), grid, block, 0, st, k, (const S*)src, (S*)dst, k0, k1,
                        ka, kb, kc);
   return hipGetLastError();
-}
-
-hipError_t launch_strip3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
-                         uint32_t key_c, hipStream_t st) {
-  if (a.storage != 1) return hipErrorInvalidValue;
-  return launch_strip3_fm<false, false>(a.f, src, dst, nullptr, nullptr, key_a, key_b, key_c, st);
 }
 
 template <typename S, int TY, int NT>

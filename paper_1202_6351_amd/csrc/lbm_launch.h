@@ -49,10 +49,10 @@ constexpr int64_t kStep3LargeMinNodes = 1 << 20;
 // intermediate step, and its segment length: the launch is cut into about
 // kStripRounds waves of resident workgroups (segments per strip =
 // kStripRounds x resident workgroups / strips), segments at least
-// kStripMinLen rows.  FP32 lattices of up to kStripMaxNodes nodes take the
-// strip kernel; larger ones, and FP64, the four-step 64 x TY tiles
-// (measured on one MI355X: the four-step tiles lead from 1024^2 up, by 10 %
-// at 2048^2 and 12 % at 4096^2).
+// kStripMinLen rows.  The kernel serves the state-keeping recompute
+// (lbm_step_sequence) of FP32 lattices of up to kStripMaxNodes nodes; plain
+// stepping takes the four-step 64 x TY tiles at every size (measured on one
+// MI355X: ahead of the strips by 5 % at 512^2 and 15 % at 1024^2).
 constexpr int kStripWaves = 4, kStripRing = 6;
 constexpr int kStripRounds = 16, kStripMinLen = 8;
 constexpr int64_t kStripMaxNodes = (int64_t)1 << 20;
@@ -64,7 +64,7 @@ constexpr int64_t kWriteBackMaxBytes = (int64_t)192 << 20;
 
 // Four-step kernel: 64 x TY tiles, NT threads per workgroup (two workgroups
 // per CU in both precisions).
-constexpr int kStep4TyF32 = 24, kStep4ThreadsF32 = 512;
+constexpr int kStep4TyF32 = 24, kStep4ThreadsF32 = 768;
 constexpr int kStep4TyF64 = 8, kStep4ThreadsF64 = 512;
 
 // Two-step kernel: 64 x 8 tiles (instead of 64 x 16) for lattices of up to
@@ -113,13 +113,10 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
 // calls.
 hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                         uint32_t key_c, hipStream_t st);
-// Strip-tiled three-step launch (FP32 only): same contract as launch_step3;
-// the tiling is g.st3.
-hipError_t launch_strip3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
-                         uint32_t key_c, hipStream_t st);
-// The same, also storing the intermediate states n+1 to keep0 and n+2 to
-// keep1 (src, keep0, keep1, dst pairwise distinct).  Same result as three
-// launch_step calls src -> keep0 -> keep1 -> dst.
+// Strip-tiled three-step launch (FP32 only; the tiling is g.st3) that also
+// stores the intermediate states n+1 to keep0 and n+2 to keep1 (src, keep0,
+// keep1, dst pairwise distinct).  Same result as three launch_step calls
+// src -> keep0 -> keep1 -> dst.
 hipError_t launch_strip3_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* dst,
                               uint32_t key_a, uint32_t key_b, uint32_t key_c, hipStream_t st);
 // Workgroups of the three-step strip kernel resident on the current device at

@@ -147,14 +147,11 @@ def test_cavity_4096_fused_launch(storage, group, tol):
 
 @pytest.mark.parametrize("shape", [(1000, 1045), (1024, 1024), (1021, 1031), (2600, 2597)])
 @pytest.mark.parametrize("case", ["cavity", "periodic_force"])
-def test_fp32_fused_kernels_either_side_of_switch(shape, case):
-    """FP32 lattices of up to 2^20 nodes fuse three steps per launch in the
-    strip kernel, larger ones four in the 64 x TY tiles: 1000 x 1045 (ragged)
-    and 1024 x 1024 (the largest strip lattice) below, 1021 x 1031 and
-    2600 x 2597 (ragged in x and y) above.  Four-, three- and two-step
-    launches each bit-exact against single steps; the cavity case also within
-    4e-7 of as many FP64 oracle steps as the main launch fuses, at sampled
-    nodes."""
+def test_fp32_fused_kernels_ragged(shape, case):
+    """FP32 four-, three- and two-step launches on 1000 x 1045, 1024 x 1024,
+    1021 x 1031 and 2600 x 2597 (ragged in x and y but 1024^2), each
+    bit-exact against single steps; the cavity case also within 4e-7 of four
+    FP64 oracle steps at sampled nodes."""
     from paper_1202_6351_amd import Lattice, Params
     nx, ny = shape
     if case == "cavity":
@@ -173,7 +170,7 @@ def test_fp32_fused_kernels_either_side_of_switch(shape, case):
     _fused_equals_single(lat, 2)  # the two-step launch of a remainder
     if case != "cavity":
         return
-    group = 3 if nx * ny <= (1 << 20) else 4
+    group = 4
     f_n = lat.populations().cpu().numpy()
     lat.step(group)
     p = oracle.Params(nx, ny, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
