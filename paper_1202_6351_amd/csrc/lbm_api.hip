@@ -124,6 +124,11 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
   g.t2_ty = storage_size(p->storage) == 8 || (int64_t)p->nx * p->ny <= lbm::kStep2SmallMaxNodes ? 8 : 16;
   g.t2_tiles_x = (int32_t)((p->nx + 63) / 64);
   g.t2_tiles_y = (int32_t)((p->ny + g.t2_ty - 1) / g.t2_ty);
+  const int64_t nodes = (int64_t)p->nx * p->ny;
+  g.t4_ty = storage_size(p->storage) == 8 ? lbm::kStep4TyF64
+            : nodes <= lbm::kStep4SmallMaxNodes ? lbm::kStep4TyF32Small
+            : nodes <= lbm::kStep4MidMaxNodes ? lbm::kStep4TyF32Mid
+                                              : lbm::kStep4TyF32;
   if (storage_size(p->storage) != 8) {
     g.t3_ty = lbm::kStep3TyF32;
     g.t3_threads = lbm::kStep3ThreadsF32;

@@ -644,14 +644,14 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
   }
 }
 
-// Four fused steps per launch (FP32 above 1 Mi nodes, FP64 at every size).
-// Step n on the tile plus a three-node ring (70 x (TY+6)) from HBM into LDS;
-// steps n+1 and n+2 in place in LDS on the tile plus a two- and a one-node
-// ring; step n+3 on the tile to HBM.  HBM traffic per update is a quarter of
-// a single step's; the rings cost
+// Four fused steps per launch (FP32 and FP64, every lattice size).  Step n
+// on the tile plus a three-node ring (70 x (TY+6)) from HBM into LDS; steps
+// n+1 and n+2 in place in LDS on the tile plus a two- and a one-node ring;
+// step n+3 on the tile to HBM.  HBM traffic per update is a quarter of a
+// single step's; the rings cost
 // (70 (TY+6) + 68 (TY+4) + 66 (TY+2) + 64 TY) / (4 * 64 TY) - 1 extra
-// collisions: 18 % at TY = 24 (FP32, 74 KB of LDS, 768 threads) and 45 % at
-// TY = 8 (FP64, 69 KB, 512 threads), two workgroups per CU in both.
+// collisions: 18 % at TY = 24 (FP32 on large lattices, 74 KB of LDS, 768
+// threads), 31 % at TY = 12 and 45 % at TY = 8 (FP64: 69 KB, 512 threads).
 template <typename S, int FM, bool SR, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
                                                S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
@@ -1426,6 +1426,12 @@ hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t 
     case 0:
       return launch_step4_fm<double, kStep4TyF64, kStep4ThreadsF64>(a.d, src, dst, key_a, key_b, key_c, key_d, st);
     case 1:
+      if (a.f.g.t4_ty == kStep4TyF32Small)
+        return launch_step4_fm<float, kStep4TyF32Small, kStep4ThreadsF32Small>(a.f, src, dst, key_a, key_b, key_c,
+                                                                               key_d, st);
+      if (a.f.g.t4_ty == kStep4TyF32Mid)
+        return launch_step4_fm<float, kStep4TyF32Mid, kStep4ThreadsF32Mid>(a.f, src, dst, key_a, key_b, key_c, key_d,
+                                                                           st);
       return launch_step4_fm<float, kStep4TyF32, kStep4ThreadsF32>(a.f, src, dst, key_a, key_b, key_c, key_d, st);
     default: return hipErrorInvalidValue;
   }

@@ -33,6 +33,7 @@ struct Geom {
   // workgroup.
   int32_t t2_ty, t2_tiles_x, t2_tiles_y;
   int32_t t3_ty, t3_tiles_x, t3_tiles_y, t3_threads;
+  int32_t t4_ty;  // four-step kernel tile height (FP32: by lattice size)
   StripTiling st2, st3;
 };
 
@@ -62,9 +63,17 @@ constexpr int64_t kStripMaxNodes = (int64_t)1 << 20;
 // bytes, so that the next launch finds the state in the last-level cache.
 constexpr int64_t kWriteBackMaxBytes = (int64_t)192 << 20;
 
-// Four-step kernel: 64 x TY tiles, NT threads per workgroup (two workgroups
-// per CU in both precisions).
+// Four-step kernel: 64 x TY tiles, NT threads per workgroup.  FP32 takes the
+// tile height by lattice size, so that smaller lattices still give the chip
+// enough workgroups: 64 x 8 (512 threads) up to kStep4SmallMaxNodes, 64 x 12
+// (768) up to kStep4MidMaxNodes, 64 x 24 (768) above.  Measured on one
+// MI355X, GLUPS at 512^2 / 724^2 / 1024^2 / 2048^2: 78.9 / 103.0 / 140.0 /
+// 179.9 with 64 x 8, 72.3 / 101.5 / 146.5 / 174.9 with 64 x 12, 67.5 / 99.9
+// / 141.7 / 189.4 with 64 x 24.
 constexpr int kStep4TyF32 = 24, kStep4ThreadsF32 = 768;
+constexpr int kStep4TyF32Mid = 12, kStep4ThreadsF32Mid = 768;
+constexpr int kStep4TyF32Small = 8, kStep4ThreadsF32Small = 512;
+constexpr int64_t kStep4SmallMaxNodes = 600000, kStep4MidMaxNodes = 1200000;
 constexpr int kStep4TyF64 = 8, kStep4ThreadsF64 = 512;
 
 // Two-step kernel: 64 x 8 tiles (instead of 64 x 16) for lattices of up to
