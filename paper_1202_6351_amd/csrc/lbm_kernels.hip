@@ -1523,6 +1523,13 @@ hipError_t launch_adjoint_step2(const KArgsAny& a, const void* prev_a, const voi
       return hipGetLastError();
     }
     case 1: {
+      if ((int64_t)g.nx * g.ny <= kAdjoint2SmallMaxNodes) {
+        constexpr int TY = kAdjoint2TyF32Small;
+        const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
+        hipLaunchKernelGGL((k_adjoint_step2<float, TY>), grid, dim3(256), 0, st, a.f, (const float*)prev_a,
+                           (const float*)prev_b, (const float*)mu_in, (float*)mu_out, (float*)grad_force);
+        return hipGetLastError();
+      }
       constexpr int TY = kAdjoint2TyF32;
       const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
       hipLaunchKernelGGL((k_adjoint_step2<float, TY>), grid, dim3(256), 0, st, a.f, (const float*)prev_a,

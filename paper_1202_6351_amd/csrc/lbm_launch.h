@@ -82,6 +82,11 @@ constexpr int64_t kStep2SmallMaxNodes = (int64_t)1 << 21;
 
 // Two-step adjoint tile heights (64 x TY tiles, 256 threads).
 constexpr int kAdjoint2TyF32 = 8, kAdjoint2TyF64 = 4;
+// FP32 lattices of up to kAdjoint2SmallMaxNodes nodes take 64 x 4 tiles, twice
+// the workgroups (measured at 512^2: 7.17 -> 6.6 us per adjoint step, the
+// rollout's backward 22.8 -> 21.4 ms; slower from 1024^2 up).
+constexpr int kAdjoint2TyF32Small = 4;
+constexpr int64_t kAdjoint2SmallMaxNodes = 600000;
 
 // Kernel arguments in the compute real R.
 template <typename R>
