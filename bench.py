@@ -61,10 +61,12 @@ VALU_FILE = os.path.join(ROOT, "profiles", "valu_step4_fp32_cavity4096.txt")
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed lane
 # instructions per second).
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# One FP32 collision without body force in the kernels' factorised form: 100
-# VALU operations (31 add, 17 sub, 13 mul, 38 fma, 1 rcp), 138 flops with an
-# fma counted as two.
-COLLISION_OPS_FP32, COLLISION_FLOPS_FP32 = 100, 138
+# One FP32 collision without body force in the kernels' factorised form, at
+# the benchmark's omega_3 = omega_6 = omega_7 = omega_8 = 1 (the multiplies by
+# omega_6..8 are then left out): 97 VALU operations (31 add, 17 sub, 10 mul,
+# 38 fma, 1 rcp), 135 flops with an fma counted as two.  With other rates:
+# 100 operations, 138 flops.
+COLLISION_OPS_FP32, COLLISION_FLOPS_FP32 = 97, 135
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # published, packed FP32 FMA
 
 

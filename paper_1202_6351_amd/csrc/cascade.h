@@ -384,8 +384,10 @@ __device__ __forceinline__ float recip(float x) {
 // first-order central moments of d are rho0 u, which stand in for the
 // products rho0 u_x, rho0 u_y of the attractors; the 2 Delta C_11, and
 // twice the outer rows of the y inverse, are carried so that the factors 1/2
-// and 1/4 of the inverse fold into the final multiply-adds.
-template <typename R, bool kForce>
+// and 1/4 of the inverse fold into the final multiply-adds.  kUnit678: the
+// caller knows omega_6 = omega_7 = omega_8 = 1 (the paper's default), so
+// their multiplies, exact identities then, are left out.
+template <typename R, bool kForce, bool kUnit678 = false>
 LBM_HD void collide_step(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9]) {
   R M[3][3];
   raw_moments(d, M);
@@ -416,9 +418,12 @@ LBM_HD void collide_step(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9]) 
   const R ad = r.hw4 * fmad(-r.rho0, p, -(C20 - C02));
   const R D20 = as + ad, D02 = as - ad;
   const R E11mC = fmad(-r.rho0, uxy, -C11);
-  const R D21 = r.w6 * fmad(r0uy, ux2 + R(1.0 / 3.0), -C21);
-  const R D12 = r.w7 * fmad(r0ux, uy2 + R(1.0 / 3.0), -C12);
-  const R D22 = r.w8 * fmad(-r.rho0, fmad(q, R(1.0 / 3.0), uxy * uxy), fmad(R(1.0 / 9.0), drho, -C22));
+  const R E21mC = fmad(r0uy, ux2 + R(1.0 / 3.0), -C21);
+  const R E12mC = fmad(r0ux, uy2 + R(1.0 / 3.0), -C12);
+  const R E22mC = fmad(-r.rho0, fmad(q, R(1.0 / 3.0), uxy * uxy), fmad(R(1.0 / 9.0), drho, -C22));
+  const R D21 = kUnit678 ? E21mC : r.w6 * E21mC;
+  const R D12 = kUnit678 ? E12mC : r.w7 * E12mC;
+  const R D22 = kUnit678 ? E22mC : r.w8 * E22mC;
   // Back to raw moments (shift by +u, y then x) and the inverse transform
   // (y then x), added to d.  B0, B2: twice the rows e_y = -1, +1 of the y
   // inverse; B1: the row e_y = 0.

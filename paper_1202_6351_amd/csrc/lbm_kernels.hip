@@ -436,7 +436,7 @@ __device__ __forceinline__ void force_at(const KArgs<R>& a, int gx, int gy, R& F
 
 // Step n for one window cell from its nine pulled populations d, rounded and
 // kept in LDS.
-template <typename S, int FM, bool SR, int EH, int EW>
+template <typename S, int FM, bool SR, int EH, int EW, bool U = false>
 __device__ __forceinline__ void collide_into_window(const KArgs<typename Codec<S>::R>& a,
                                                     const Rates<typename Codec<S>::R>& rt, int gx, int gy,
                                                     const typename Codec<S>::R d[9], uint32_t key,
@@ -445,7 +445,7 @@ __device__ __forceinline__ void collide_into_window(const KArgs<typename Codec<S
   R Fx, Fy;
   force_at<FM>(a, gx, gy, Fx, Fy);
   R out[9];
-  collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+  collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
   S o[9];
   round_out<S, SR>(out, (uint32_t)(gy * a.g.nx + gx), key, o);
 #pragma unroll
@@ -473,7 +473,7 @@ __device__ __forceinline__ void pull_hbm(const KArgs<typename Codec<S>::R>& a, _
 // unwrapped coordinates) from HBM into LDS, one cell at a time.  fast: no
 // cell of the window pulls across a wall or a wrap, and the lattice is below
 // 4 GiB.
-template <typename S, int FM, bool SR, int EH, int EW>
+template <typename S, int FM, bool SR, int EH, int EW, bool U = false>
 __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
                                                int wx0, int wy0, bool fast, uint32_t key, S (&mid)[9][EH][EW]) {
@@ -485,14 +485,14 @@ __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>
     if (!window_node(a.g, wx0 + cx, wy0 + cy, gx, gy)) continue;
     R d[9];
     pull_hbm<S>(a, rs, src, fast, gx, gy, d);
-    collide_into_window<S, FM, SR, EH, EW>(a, rt, gx, gy, d, key, mid, cx, cy);
+    collide_into_window<S, FM, SR, EH, EW, U>(a, rt, gx, gy, d, key, mid, cx, cy);
   }
 }
 
 // The same with every load of the thread's cells issued before the first
 // collision, so that HBM latency is paid once per stage rather than once per
 // cell.
-template <typename S, int FM, bool SR, int EH, int EW, int NT>
+template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U = false>
 __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Codec<S>::R>& a,
                                                         const Rates<typename Codec<S>::R>& rt,
                                                         const S* __restrict__ src, int wx0, int wy0, bool fast,
@@ -513,7 +513,7 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int i = (int)threadIdx.x + NT * j;
-    if (live[j]) collide_into_window<S, FM, SR, EH, EW>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW);
+    if (live[j]) collide_into_window<S, FM, SR, EH, EW, U>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW);
   }
 }
 
@@ -522,7 +522,7 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 // collides its cells into registers; after a barrier it writes them back.
 // WALLS = false: the window lies inside the domain and no cell's link
 // crosses a wall.
-template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT>
+template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U = false>
 __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
                                              uint32_t key, S (&mid)[9][EH][EW]) {
@@ -543,7 +543,7 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
     R Fx, Fy;
     force_at<FM>(a, gx, gy, Fx, Fy);
     R out[9];
-    collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+    collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
     round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key, o[j]);
   }
   __syncthreads();
@@ -559,7 +559,7 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
 }
 
 // Last stage: one step on the 64 x TY tile from LDS to HBM.
-template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT>
+template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U = false>
 __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int x0, int y0,
                                              uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst) {
@@ -574,7 +574,7 @@ __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& 
     R Fx, Fy;
     force_at<FM>(a, gx, gy, Fx, Fy);
     R out[9];
-    collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
+    collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
     S o[9];
     round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key, o);
     store_node<S>(g, dst, gx, gy, o);
@@ -599,7 +599,7 @@ __device__ __forceinline__ void tile_origin(const Geom& g, int tiles_x, int& x0,
 // to HBM.  HBM traffic per update is halved; the ring costs
 // (66 (TY+2)) / (64 TY) - 1 = 16 % (TY = 16) extra collisions, and its loads
 // hit L2 (neighbouring tiles run on the same XCD).
-template <typename S, int FM, bool SR, int TY>
+template <typename S, int FM, bool SR, int TY, bool U>
 __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
                                                S* __restrict__ dst, uint32_t key_a, uint32_t key_b) {
   constexpr int H = 1, EW = 64 + 2 * H, EH = TY + 2 * H;
@@ -608,12 +608,12 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t2_tiles_x, x0, y0, interior, fast);
-  stage_from_hbm<S, FM, SR, EH, EW>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  stage_from_hbm<S, FM, SR, EH, EW, U>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
   if (interior)  // workgroup-uniform
-    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, 256>(a, rt, x0, y0, key_b, mid, dst);
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, 256, U>(a, rt, x0, y0, key_b, mid, dst);
   else
-    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, 256>(a, rt, x0, y0, key_b, mid, dst);
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, 256, U>(a, rt, x0, y0, key_b, mid, dst);
 }
 
 // Three fused steps per launch.  Step n on the tile plus a two-node ring
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
 // (70 (TY+6) + 68 (TY+4) + 66 (TY+2) + 64 TY) / (4 * 64 TY) - 1 extra
 // collisions: 18 % at TY = 24 (FP32 on large lattices, 74 KB of LDS, 768
 // threads), 31 % at TY = 12 and 45 % at TY = 8 (FP64: 69 KB, 512 threads).
-template <typename S, int FM, bool SR, int TY, int NT>
+template <typename S, int FM, bool SR, int TY, int NT, bool U>
 __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
                                                S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
                                                uint32_t key_c, uint32_t key_d) {
@@ -662,16 +662,16 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, U>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
   if (interior) {  // workgroup-uniform: every thread meets the same barriers
-    stage_in_lds<false, S, FM, SR, EH, EW, H, 2, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
-    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_c, mid);
-    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_d, mid, dst);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT, U>(a, rt, x0, y0, key_d, mid, dst);
   } else {
-    stage_in_lds<true, S, FM, SR, EH, EW, H, 2, NT>(a, rt, x0 - H, y0 - H, key_b, mid);
-    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT>(a, rt, x0 - H, y0 - H, key_c, mid);
-    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT>(a, rt, x0, y0, key_d, mid, dst);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT, U>(a, rt, x0, y0, key_d, mid, dst);
   }
 }
 
@@ -1307,17 +1307,33 @@ static hipError_t launch_step_fm(const KArgs<typename Codec<S>::R>& k, const voi
   return hipGetLastError();
 }
 
-template <typename S, bool SR, int TY>
-static void launch_step2_ty(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                            uint32_t kb, hipStream_t st) {
+// omega_6 = omega_7 = omega_8 = 1 (the paper's default): the collision leaves
+// out their multiplies (exact identities), same results bit for bit.
+template <typename R>
+static bool unit678(const KArgs<R>& k) {
+  return k.w[3] == R(1) && k.w[4] == R(1) && k.w[5] == R(1);
+}
+
+template <typename S, bool SR, int TY, bool U>
+static void launch_step2_tyu(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                             uint32_t kb, hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(k.g.t2_tiles_x * k.g.t2_tiles_y));
   if (fm == 0)
-    hipLaunchKernelGGL((k_step2<S, 0, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+    hipLaunchKernelGGL((k_step2<S, 0, SR, TY, U>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
   else if (fm == 1)
-    hipLaunchKernelGGL((k_step2<S, 1, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+    hipLaunchKernelGGL((k_step2<S, 1, SR, TY, U>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
   else
-    hipLaunchKernelGGL((k_step2<S, 2, SR, TY>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+    hipLaunchKernelGGL((k_step2<S, 2, SR, TY, U>), grid, dim3(256), 0, st, k, (const S*)src, (S*)dst, ka, kb);
+}
+
+template <typename S, bool SR, int TY>
+static void launch_step2_ty(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                            uint32_t kb, hipStream_t st) {
+  if (unit678(k))
+    launch_step2_tyu<S, SR, TY, true>(k, src, dst, ka, kb, st);
+  else
+    launch_step2_tyu<S, SR, TY, false>(k, src, dst, ka, kb, st);
 }
 
 // Tile height 8 (FP64 always, the other storages on small lattices) or 16.
@@ -1403,21 +1419,28 @@ static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void*
   return hipGetLastError();
 }
 
-template <typename S, int TY, int NT>
-static hipError_t launch_step4_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                                  uint32_t kb, uint32_t kc, uint32_t kd, hipStream_t st) {
+template <typename S, int TY, int NT, bool U>
+static hipError_t launch_step4_fmu(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                   uint32_t kb, uint32_t kc, uint32_t kd, hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(k.g.t3_tiles_x * ((k.g.ny + TY - 1) / TY)));
   if (fm == 0)
-    hipLaunchKernelGGL((k_step4<S, 0, false, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc,
-                       kd);
+    hipLaunchKernelGGL((k_step4<S, 0, false, TY, NT, U>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
+                       kc, kd);
   else if (fm == 1)
-    hipLaunchKernelGGL((k_step4<S, 1, false, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc,
-                       kd);
+    hipLaunchKernelGGL((k_step4<S, 1, false, TY, NT, U>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
+                       kc, kd);
   else
-    hipLaunchKernelGGL((k_step4<S, 2, false, TY, NT>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb, kc,
-                       kd);
+    hipLaunchKernelGGL((k_step4<S, 2, false, TY, NT, U>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
+                       kc, kd);
   return hipGetLastError();
+}
+
+template <typename S, int TY, int NT>
+static hipError_t launch_step4_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
+                                  uint32_t kb, uint32_t kc, uint32_t kd, hipStream_t st) {
+  return unit678(k) ? launch_step4_fmu<S, TY, NT, true>(k, src, dst, ka, kb, kc, kd, st)
+                    : launch_step4_fmu<S, TY, NT, false>(k, src, dst, ka, kb, kc, kd, st);
 }
 
 hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
