@@ -18,8 +18,8 @@ adjoint at once).  The backward recomputes each older segment's states from
 its snapshot and runs the adjoint over them newest-first.  The recompute of
 the next (older) segment runs on one stream while the adjoint of the current
 one runs on another, so the two kernels share the GPU; they alternate
-between two sets of `checkpoint_every` lattice buffers (the forward's set and
-one more), each set one allocation.  Both streams are ordinary streams
+between two sets of lattice buffers (the forward's set and one more of
+`checkpoint_every - 1`), each set one allocation.  Both streams are ordinary streams
 kept per device (not the legacy default stream, whose implicit
 synchronisation with other streams serialised the two).  Work per step of
 the backward: one recomputed step and one adjoint step.
@@ -82,8 +82,10 @@ class Rollout(torch.autograd.Function):
                 break
             if s == nseg - 1 and any(ctx.needs_input_grad[:2]):
                 # the last segment keeps its states for the backward; its
-                # final state becomes the lattice's current state
-                keep_base, keep = _lattice_set(lat, every)
+                # final state becomes the lattice's current state.  The set
+                # later serves the backward's recomputes of older segments
+                # (every - 1 states each).
+                keep_base, keep = _lattice_set(lat, n if nseg == 1 else max(n, every - 1))
                 lat.step_sequence(snaps[s], keep[:n])
                 lat.restore(keep[n - 1], steps)
             else:
