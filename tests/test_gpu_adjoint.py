@@ -395,8 +395,9 @@ def test_handle_on_another_stream():
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_step_sequence_with_reused_buffers(pattern, storage):
     """lbm_step_sequence may reuse a buffer once its state has been read.  In
-    FP32 the library fuses groups of three steps (storing the intermediate
-    states) only when the group's four buffers are distinct and falls back
+    FP32 lattices of up to 2^20 nodes the library fuses groups of three steps
+    (storing the intermediate states) only when the group's four buffers are
+    distinct and falls back
     to single steps otherwise: ping-pong buffers never fuse, a cycle of
     three fuses once, a cycle of four twice.  Every buffer ends holding the
     state last written into it, as with single steps."""
@@ -463,9 +464,9 @@ def test_rollout_forward_same_with_and_without_gradient(storage, T, every):
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 def test_step_sequence_large_shape(storage):
-    """lbm_step_sequence on 1030 x 1030 (FP64 takes its large three-step
-    shape there), walls and lid, force field: seven kept states equal seven
-    lbm_step_between calls bit for bit."""
+    """lbm_step_sequence on 1030 x 1030 (above 2^20 nodes, where every
+    precision runs it as single steps), walls and lid, force field: seven
+    kept states equal seven lbm_step_between calls bit for bit."""
     nx = ny = 1030
     bc, wu = BCS[2]
     lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=12), storage=storage, tau=0.6, bc=bc, wall_u=wu)

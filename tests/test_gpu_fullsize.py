@@ -11,10 +11,11 @@ difference is the GPU's own arithmetic and storage rounding for one step:
   FP32   <= 1e-7 absolute (FP32 arithmetic on deviations of order 1e-2),
   16-bit <= half an ulp of the stored deviation + 1e-7 (round to nearest).
 
-The launch the benchmark times fuses steps (three per launch in FP32 and
+The launch the benchmark times fuses steps (four per launch in FP32 and
 FP64, two in 16-bit).  At the same sizes, one fused launch is checked against
 single steps bit for bit on the raw lattice buffers, and for FP32/FP64 a
-three-step launch from a read-back state against three full oracle steps.
+four- or three-step launch from a read-back state against as many full
+oracle steps.
 """
 import numpy as np
 import pytest

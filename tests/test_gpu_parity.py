@@ -199,10 +199,12 @@ def test_diagnostics_detect_instability():
 @pytest.mark.parametrize("force", ["none", "uniform", "field"])
 @pytest.mark.parametrize("n", [5, 7])
 def test_multi_step_launch_equals_single_steps(storage, rounding, shape, bci, force, n):
-    """lbm_step(n) fuses steps in launches of three (FP64, FP32: 5 = 3 + 2,
-    7 = 3 + 3 + 1) or two (16-bit: 5 = 2 + 2 + 1, 7 = 2 + 2 + 2 + 1), the
+    """lbm_step(n) fuses steps in launches of four (FP64, FP32: 5 = 4 + 1,
+    7 = 4 + 3) or two (16-bit: 5 = 2 + 2 + 1, 7 = 2 + 2 + 2 + 1), the
     intermediate states kept in LDS; it must give bit-for-bit the state of n
-    single-step launches."""
+    single-step launches.  The rates omega_6, omega_7 differ from 1, so the
+    fused kernels take their general collision (the default rates take the
+    variant without those multiplies, covered by the full-size tests)."""
     from paper_1202_6351_amd import Lattice, Params
     nx, ny = shape
     bc, wu = BCS[bci]
@@ -226,9 +228,10 @@ def test_multi_step_launch_equals_single_steps(storage, rounding, shape, bci, fo
 @pytest.mark.parametrize("bci", [0, 1, 3])
 @pytest.mark.parametrize("force", ["none", "field"])
 def test_multi_step_launch_large_shape(storage, bci, force):
-    """Above a million nodes FP64 runs its three-step launch with the large
-    workgroup shape; 1030 x 1030 (ragged against every tile size), seven
-    steps, bit-for-bit seven single steps."""
+    """1030 x 1030 (ragged against every tile size; above a million nodes,
+    where FP64 takes its large three-step shape and FP32 its 64 x 12
+    four-step tiles): seven steps (a four-step and a three-step launch),
+    bit-for-bit seven single steps."""
     from paper_1202_6351_amd import Lattice, Params
     nx = ny = 1030
     bc, wu = BCS[bci]
