@@ -198,7 +198,7 @@ lbm_status lbm_step_between(lbm_ctx* ctx, const void* src, void* dst);
  * input (src for states[0], states[i-1] for states[i]); a buffer may be
  * reused once its state has been read (ping-pong).  The segment recompute
  * of a checkpointed adjoint.  Same result as n calls of lbm_step_between
- * (groups of three steps whose four buffers are distinct may run as one
+ * (groups of four steps whose five buffers are distinct may run as one
  * fused launch).  Does not change lbm_time or the current lattice. */
 lbm_status lbm_step_sequence(lbm_ctx* ctx, const void* src, void* const* states, int64_t n);
 

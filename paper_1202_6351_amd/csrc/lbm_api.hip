@@ -24,7 +24,6 @@ struct lbm_ctx {
   double* diag_scratch;  // device: partial sums (diag_blocks * 4) + result (4); first diagnostics call
   int diag_blocks;
   int64_t pitch, lattice_bytes;
-  bool strip3;        // state-keeping sequences take the three-step strip kernel
   char err[512];
 };
 
@@ -206,24 +205,6 @@ lbm_status lbm_lattice_layout(const lbm_params* p, int64_t* pitch, int64_t* byte
   return LBM_OK;
 }
 
-// Strip tiling of a fused launch of `steps` steps: strips of 64 - 2 (steps -
-// 1) columns, cut into segments so that all workgroups of the launch are
-// resident at once (one wave of workgroups, no tail), each segment a multiple
-// of `waves` rows and at least kStripMinLen.
-static lbm::StripTiling strip_tiling(int nx, int ny, int steps, int waves, int resident) {
-  lbm::StripTiling t;
-  const int tw = 64 - 2 * (steps - 1);
-  t.strips = (nx + tw - 1) / tw;
-  const int per = lbm::kStripRounds * resident / t.strips;
-  const int per_strip = per > 1 ? per : 1;
-  int len = (ny + per_strip - 1) / per_strip;
-  len = (len + waves - 1) / waves * waves;
-  if (len < lbm::kStripMinLen) len = lbm::kStripMinLen;
-  t.len = len;
-  t.segs = (ny + len - 1) / len;
-  return t;
-}
-
 lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* force_field,
                       void* stream, lbm_ctx** out) {
   if (!out) { set_err(g_create_err, "out is NULL"); return LBM_EINVAL; }
@@ -250,11 +231,6 @@ lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* f
   c->args.stochastic = p->rounding == LBM_ROUND_STOCHASTIC;
   if (p->storage == LBM_FP64) fill_args<double>(p, c->pitch, force_field, c->args.d);
   else fill_args<float>(p, c->pitch, force_field, c->args.f);
-  c->strip3 = p->storage == LBM_FP32 && (int64_t)p->nx * p->ny <= lbm::kStripMaxNodes;
-  if (c->strip3) {
-    const int resident = lbm::strip3_resident();
-    c->args.f.g.st3 = strip_tiling(p->nx, p->ny, 3, lbm::kStripWaves, resident > 0 ? resident : 1280);
-  }
   // Diagnostics: a fixed number of blocks (enough to fill 256 CUs), so the
   // reduction order does not depend on the grid size.
   c->diag_blocks = 1024;
@@ -373,17 +349,23 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
     if (!states[i] || states[i] == prev) return inval(c, "step_sequence: states[i] NULL or equal to its input");
     if (!aligned(states[i])) return inval(c, "step_sequence: buffers must be 256-byte aligned");
   }
-  // FP32 lattices that take the strip kernel run groups of three steps as
-  // one launch that also stores the two intermediate states, as long as the
-  // group's four buffers are distinct; the rest runs as single steps.
+  // FP32 lattices of up to kStep4MidMaxNodes nodes run groups of four steps
+  // as one four-step launch that also stores the three intermediate states,
+  // as long as the group's five buffers are distinct; the rest runs as
+  // single steps.
   const uint32_t key = step_key(c->p, c->t);
   int64_t i = 0;
-  for (; c->strip3 && i + 3 <= n; i += 3) {
+  const bool tiles4 = c->p.storage == LBM_FP32 && (int64_t)c->p.nx * c->p.ny <= lbm::kStep4MidMaxNodes;
+  for (; tiles4 && i + 4 <= n; i += 4) {
     const void* in = i == 0 ? src : states[i - 1];
-    void *k0 = states[i], *k1 = states[i + 1], *out = states[i + 2];
-    if (in == k1 || in == out || k0 == k1 || k0 == out || k1 == out) break;  // in != k0 checked above
-    lbm_status s = dev_err(c, lbm::launch_strip3_keep(c->args, in, k0, k1, out, key, key, key, c->stream),
-                           "three-step kernel");
+    void *k0 = states[i], *k1 = states[i + 1], *k2 = states[i + 2], *out = states[i + 3];
+    const void* b[5] = {in, k0, k1, k2, out};
+    bool distinct = true;
+    for (int p = 0; p < 5; ++p)
+      for (int q = p + 1; q < 5; ++q) distinct = distinct && b[p] != b[q];
+    if (!distinct) break;
+    lbm_status s = dev_err(c, lbm::launch_step4_keep(c->args, in, k0, k1, k2, out, key, key, key, key, c->stream),
+                           "four-step kernel");
     if (s != LBM_OK) return s;
   }
   for (; i < n; ++i) {

@@ -21,11 +21,8 @@
 // The fused launches keep intermediate steps in LDS, so the state crosses
 // HBM once per two, three or four steps.  k_step2, k_step3 and k_step4 give
 // each workgroup a 64 x TY tile plus a recompute ring (two, three or four
-// steps); k_strip gives it a strip of 60 columns that it walks down row by
-// row, one wavefront per row and step, the intermediate rows in small LDS
-// rings, so that only the strip's sides are recomputed (three steps that
-// also store both intermediate states: the state-keeping recompute of FP32
-// lattices up to 1 Mi nodes).  In every kernel the 1-D block index is remapped so that each of
+// steps); k_step4 can also store its intermediate states (the state-keeping
+// recompute of the adjoint).  In every kernel the 1-D block index is remapped so that each of
 // the 8 XCDs (blocks are dealt to XCDs round-robin) processes one contiguous
 // band of tiles, keeping the lines shared between horizontally and
 // vertically adjacent tiles in one L2.
@@ -436,20 +433,29 @@ __device__ __forceinline__ void force_at(const KArgs<R>& a, int gx, int gy, R& F
 
 // Step n for one window cell from its nine pulled populations d, rounded and
 // kept in LDS.
-template <typename S, int FM, bool SR, int EH, int EW, bool U = false>
+// FW: also keep the cell's force in the LDS array fw ([2][EH][EW]) for the
+// later stages.  keep (not null): also store the result there, at (gx, gy).
+template <typename S, int FM, bool SR, int EH, int EW, bool U = false, bool FW = false>
 __device__ __forceinline__ void collide_into_window(const KArgs<typename Codec<S>::R>& a,
                                                     const Rates<typename Codec<S>::R>& rt, int gx, int gy,
                                                     const typename Codec<S>::R d[9], uint32_t key,
-                                                    S (&mid)[9][EH][EW], int cx, int cy) {
+                                                    S (&mid)[9][EH][EW], int cx, int cy,
+                                                    typename Codec<S>::R* fw = nullptr,
+                                                    S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
   R Fx, Fy;
   force_at<FM>(a, gx, gy, Fx, Fy);
+  if constexpr (FW) {
+    fw[cy * EW + cx] = Fx;
+    fw[EH * EW + cy * EW + cx] = Fy;
+  }
   R out[9];
   collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
   S o[9];
   round_out<S, SR>(out, (uint32_t)(gy * a.g.nx + gx), key, o);
 #pragma unroll
   for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[k];
+  if (keep) store_kept<S>(a.g, keep, gx, gy, o);
 }
 
 // Pull of window cell (gx, gy) for the first stage: from HBM, through the
@@ -492,11 +498,17 @@ __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>
 // The same with every load of the thread's cells issued before the first
 // collision, so that HBM latency is paid once per stage rather than once per
 // cell.
-template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U = false>
+// FW: keep the window's force in fw (see collide_into_window).  KEEP: store
+// the step's result for the tile's nodes (window cells [H, EW - H) x
+// [H, EH - H) inside the domain) to keep.
+template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U = false, bool FW = false, bool KEEP = false>
 __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Codec<S>::R>& a,
                                                         const Rates<typename Codec<S>::R>& rt,
                                                         const S* __restrict__ src, int wx0, int wy0, bool fast,
-                                                        uint32_t key, S (&mid)[9][EH][EW]) {
+                                                        uint32_t key, S (&mid)[9][EH][EW],
+                                                        typename Codec<S>::R* fw = nullptr,
+                                                        S* __restrict__ keep = nullptr) {
+  constexpr int H = (EW - 64) / 2;
   using R = typename Codec<S>::R;
   constexpr int NPT = (EW * EH + NT - 1) / NT;
   const __amdgpu_buffer_rsrc_t rs = rsrc(src, a.g.lattice_bytes);
@@ -513,7 +525,14 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int i = (int)threadIdx.x + NT * j;
-    if (live[j]) collide_into_window<S, FM, SR, EH, EW, U>(a, rt, gx[j], gy[j], d[j], key, mid, i % EW, i / EW);
+    const int cx = i % EW, cy = i / EW;
+    S* kp = nullptr;
+    if constexpr (KEEP) {
+      const bool tile = cx >= H && cx < EW - H && cy >= H && cy < EH - H && wx0 + cx < a.g.nx &&
+                        wy0 + cy < a.g.ny;
+      kp = tile ? keep : nullptr;
+    }
+    if (live[j]) collide_into_window<S, FM, SR, EH, EW, U, FW>(a, rt, gx[j], gy[j], d[j], key, mid, cx, cy, fw, kp);
   }
 }
 
@@ -522,10 +541,15 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 // collides its cells into registers; after a barrier it writes them back.
 // WALLS = false: the window lies inside the domain and no cell's link
 // crosses a wall.
-template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U = false>
+// FW: forces from fw instead of the force field.  KEEP: store the results of
+// the tile's nodes to keep.
+template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U = false,
+          bool FW = false, bool KEEP = false>
 __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
-                                             uint32_t key, S (&mid)[9][EH][EW]) {
+                                             uint32_t key, S (&mid)[9][EH][EW],
+                                             const typename Codec<S>::R* fw = nullptr,
+                                             S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
   constexpr int RW = EW - 2 * (H - RING), RH = EH - 2 * (H - RING), NPT = (RW * RH + NT - 1) / NT;
   const Geom& g = a.g;
@@ -541,7 +565,12 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
     R d[9];
     pull_window<WALLS, S, R, EH, EW>(a, gx, gy, mid, cx, cy, d);
     R Fx, Fy;
-    force_at<FM>(a, gx, gy, Fx, Fy);
+    if constexpr (FW) {
+      Fx = fw[cy * EW + cx];
+      Fy = fw[EH * EW + cy * EW + cx];
+    } else {
+      force_at<FM>(a, gx, gy, Fx, Fy);
+    }
     R out[9];
     collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
     round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key, o[j]);
@@ -554,15 +583,23 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
     const int cx = H - RING + i % RW, cy = H - RING + i / RW;
 #pragma unroll
     for (int k = 0; k < 9; ++k) mid[k][cy][cx] = o[j][k];
+    if constexpr (KEEP) {
+      const int ux = wx0 + cx, uy = wy0 + cy;  // a tile node is its own position
+      if (cx >= H && cx < EW - H && cy >= H && cy < EH - H && ux < g.nx && uy < g.ny)
+        store_kept<S>(g, keep, ux, uy, o[j]);
+    }
   }
   __syncthreads();
 }
 
 // Last stage: one step on the 64 x TY tile from LDS to HBM.
-template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U = false>
+// FW: forces from fw instead of the force field.
+template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U = false,
+          bool FW = false>
 __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int x0, int y0,
-                                             uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst) {
+                                             uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst,
+                                             const typename Codec<S>::R* fw = nullptr) {
   using R = typename Codec<S>::R;
   const Geom& g = a.g;
   const int lx = (int)threadIdx.x & 63;
@@ -572,7 +609,12 @@ __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& 
     R d[9];
     pull_window<WALLS, S, R, EH, EW>(a, gx, gy, mid, lx + H, ly + H, d);
     R Fx, Fy;
-    force_at<FM>(a, gx, gy, Fx, Fy);
+    if constexpr (FW) {
+      Fx = fw[(ly + H) * EW + lx + H];
+      Fy = fw[EH * EW + (ly + H) * EW + lx + H];
+    } else {
+      force_at<FM>(a, gx, gy, Fx, Fy);
+    }
     R out[9];
     collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
     S o[9];
@@ -652,284 +694,40 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
 // (70 (TY+6) + 68 (TY+4) + 66 (TY+2) + 64 TY) / (4 * 64 TY) - 1 extra
 // collisions: 18 % at TY = 24 (FP32 on large lattices, 74 KB of LDS, 768
 // threads), 31 % at TY = 12 and 45 % at TY = 8 (FP64: 69 KB, 512 threads).
-template <typename S, int FM, bool SR, int TY, int NT, bool U>
+// With a force field (FM = 2) on FP32 tiles of up to 12 rows, the first stage
+// also keeps the window's force in LDS (fw, 8-10 KB more, still two
+// workgroups per CU), so that the later stages load nothing from memory.
+// KEEP: the intermediate states n+1, n+2, n+3 of the tile's nodes are also
+// stored to keep0, keep1, keep2 (the state-keeping recompute); the later
+// stages then issue no load after those stores, which would otherwise wait
+// for them (loads and stores share one completion counter).
+template <typename S, int FM, bool SR, int TY, int NT, bool U, bool KEEP>
 __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
-                                               S* __restrict__ dst, uint32_t key_a, uint32_t key_b,
+                                               S* __restrict__ dst, S* __restrict__ keep0, S* __restrict__ keep1,
+                                               S* __restrict__ keep2, uint32_t key_a, uint32_t key_b,
                                                uint32_t key_c, uint32_t key_d) {
+  using R = typename Codec<S>::R;
   constexpr int H = 3, EW = 64 + 2 * H, EH = TY + 2 * H;
+  constexpr bool FW = FM == 2 && sizeof(S) == 4 && TY <= 12;
   __shared__ S mid[9][EH][EW];
+  __shared__ R fwin[FW ? 2 * EH * EW : 1];
+  R* fw = FW ? fwin : nullptr;
   const auto rt = rates(a);
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, U>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
+  stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, U, FW, KEEP>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid, fw,
+                                                               keep0);
   __syncthreads();
   if (interior) {  // workgroup-uniform: every thread meets the same barriers
-    stage_in_lds<false, S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
-    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
-    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT, U>(a, rt, x0, y0, key_d, mid, dst);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 2, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_b, mid, fw, keep1);
+    stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_c, mid, fw, keep2);
+    stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT, U, FW>(a, rt, x0, y0, key_d, mid, dst, fw);
   } else {
-    stage_in_lds<true, S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
-    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
-    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT, U>(a, rt, x0, y0, key_d, mid, dst);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 2, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_b, mid, fw, keep1);
+    stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_c, mid, fw, keep2);
+    stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT, U, FW>(a, rt, x0, y0, key_d, mid, dst, fw);
   }
-}
-
-// ------------------------------------------------------------ strip kernels
-// NS fused steps per launch, tiled in strips.  A workgroup of NW wavefronts
-// owns the TW = 64 - 2 (NS - 1) columns [x0, x0 + TW) of rows [ys, ye) and
-// walks down them, NW rows per iteration.  Each wavefront works on one window
-// row of 64 nodes per step; lane l holds window column x0 - (NS - 1) + l.  In
-// an iteration where the wavefront's step-0 row is r0, step s computes lanes
-// [s, 64 - s) of row r0 - s: step 0 pulls from HBM, step s > 0 from the LDS
-// ring holding step s - 1 (rows r - 1 .. r + 1), the last step stores to HBM.
-// The halo is recomputed only at the strip's sides (2 (NS - 1) of 64 lanes)
-// and at the segment's two ends, never between consecutive rows.
-//
-// Ring sizes: with a barrier after every step but the last, at most NW + 2
-// rows of an intermediate step are alive at once (the NW rows just computed
-// and the two below them).  With NS = 2 the next iteration's step 0 overlaps
-// the last step of this one, so its ring needs 2 NW + 2 rows.
-template <int RING>
-__device__ __forceinline__ int ring_slot(int r) {
-  return (r + 8 * RING) % RING;  // r >= -8 for every row a segment touches
-}
-
-// The nine populations streaming into node (gx, gy) held at lane l of window
-// row r, pulled from the ring of the previous step; sm, s0, sp are the slots
-// of rows r - 1, r, r + 1.
-template <bool WALLS, typename S, typename R, int RING>
-__device__ __forceinline__ void pull_ring(const KArgs<R>& a, int gx, int gy, const S (&rg)[9][RING][64], int l,
-                                          int sm, int s0, int sp, R d[9]) {
-  const int row[3] = {sp, s0, sm};  // indexed by e_y + 1: the source row is r - e_y
-  if constexpr (!WALLS) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(rg[k][row[EY[k] + 1]][l - EX[k]]);
-    return;
-  }
-  const Edges e = edges(a.g, gx, gy);
-#define LBM_PULL_RING(A)                                                                       \
-  {                                                                                            \
-    constexpr int ax = EX[A], ay = EY[A];                                                      \
-    const bool hx = (ax == 1 && e.wxl) || (ax == -1 && e.wxh);                                 \
-    const bool hy = (ay == 1 && e.wyl) || (ay == -1 && e.wyh);                                 \
-    const R add = hx == hy ? R(0)                                                              \
-                           : (hx ? a.wadd[(ax == 1 ? 0 : 1) * 9 + A]                           \
-                                 : a.wadd[(ay == 1 ? 2 : 3) * 9 + A]);                         \
-    d[A] = (hx || hy) ? Codec<S>::load(rg[OPP[A]][s0][l]) + add                                \
-                      : Codec<S>::load(rg[A][row[ay + 1]][l - ax]);                            \
-  }
-  LBM_PULL_RING(0) LBM_PULL_RING(1) LBM_PULL_RING(2) LBM_PULL_RING(3) LBM_PULL_RING(4)
-  LBM_PULL_RING(5) LBM_PULL_RING(6) LBM_PULL_RING(7) LBM_PULL_RING(8)
-#undef LBM_PULL_RING
-}
-
-// Step-0 pulls of this wavefront's row in iteration it, into d; false if
-// the row is past the segment's window or the lane's node lies beyond a wall.
-template <typename S, int NS, int NW>
-__device__ __forceinline__ bool strip_fetch(const KArgs<typename Codec<S>::R>& a, const S* __restrict__ src,
-                                            int it, int ys, int ye, int w, int wx, int& gx, int& gy,
-                                            typename Codec<S>::R d[9]) {
-  const int r0 = ys - (NS - 1) + it * NW + w;
-  const bool in = window_node(a.g, wx, r0, gx, gy);
-  if (r0 >= ye + NS - 1 || !in) return false;
-  gather<S>(a.g, a.wadd, src, gx, gy, d);
-  return true;
-}
-
-// Strip walk of a workgroup whose window touches a wall or wraps: every
-// node resolves its links and wrapped position as the single step does.
-// The step-0 pulls of iteration it + 1 are issued before the work of
-// iteration it.
-template <typename S, int FM, bool SR, int NS, int NW, int RING, bool KEEP>
-__device__ __forceinline__ void strip_walk_edge(const KArgs<typename Codec<S>::R>& a,
-                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
-                                                S* __restrict__ dst, S* const (&keep)[2], const uint32_t (&key)[3],
-                                                int x0, int ys, int ye, S (&rg)[NS - 1][9][RING][64]) {
-  using R = typename Codec<S>::R;
-  const Geom& g = a.g;
-  const int lane = (int)threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int wx = x0 - (NS - 1) + lane;  // window column of this lane (unwrapped)
-  const int nit = (ye - ys + 2 * (NS - 1) + NW - 1) / NW;
-  R dc[9];
-  int gxc = 0, gyc = 0;
-  bool lc = strip_fetch<S, NS, NW>(a, src, 0, ys, ye, w, wx, gxc, gyc, dc);
-  for (int it = 0; it < nit; ++it) {
-    const int r0 = ys - (NS - 1) + it * NW + w;  // wavefront-uniform
-    R dn[9];
-    int gxn = 0, gyn = 0;
-    const bool ln = it + 1 < nit && strip_fetch<S, NS, NW>(a, src, it + 1, ys, ye, w, wx, gxn, gyn, dn);
-    if (lc) {
-      R Fx, Fy;
-      force_at<FM>(a, gxc, gyc, Fx, Fy);
-      R out[9];
-      collide_step<R, FM != 0>(rt, Fx, Fy, dc, out);
-      S o[9];
-      round_out<S, SR>(out, (uint32_t)(gyc * g.nx + gxc), key[0], o);
-      const int sl = ring_slot<RING>(r0);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) rg[0][k][sl][lane] = o[k];
-      if (KEEP && r0 >= ys && r0 < ye && lane >= NS - 1 && lane < 64 - (NS - 1) && wx < g.nx)
-        store_kept<S>(g, keep[0], gxc, gyc, o);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 1; s < NS; ++s) {
-      const int r = r0 - s;
-      if (r >= ys - (NS - 1 - s) && r < ye + (NS - 1 - s) && lane >= s && lane < 64 - s) {
-        int gx = wx, gy = r;
-        bool live = window_node(g, wx, r, gx, gy);
-        if (s == NS - 1) live = live && wx < g.nx;  // ragged last strip: no output past the domain
-        if (live) {
-          R d[9];
-          pull_ring<true, S, R, RING>(a, gx, gy, rg[s - 1], lane, ring_slot<RING>(r - 1), ring_slot<RING>(r),
-                                      ring_slot<RING>(r + 1), d);
-          R Fx, Fy;
-          force_at<FM>(a, gx, gy, Fx, Fy);
-          R out[9];
-          collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
-          S o[9];
-          round_out<S, SR>(out, (uint32_t)(gy * g.nx + gx), key[s], o);
-          if (s < NS - 1) {
-            const int sl = ring_slot<RING>(r);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) rg[s < NS - 1 ? s : 0][k][sl][lane] = o[k];
-            if (KEEP && r >= ys && r < ye && lane >= NS - 1 && lane < 64 - (NS - 1) && wx < g.nx)
-              store_kept<S>(g, keep[s < NS - 1 ? s : 0], gx, gy, o);
-          } else {
-            const int64_t c = (int64_t)gy * g.pitch + gx;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) dst[(int64_t)k * g.plane + c] = o[k];
-          }
-        }
-      }
-      if (s < NS - 1) __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) dc[k] = dn[k];
-    gxc = gxn;
-    gyc = gyn;
-    lc = ln;
-  }
-}
-
-// Interior strip walk on the buffer path: no node of the window has a wall
-// link or wraps, and the lattice is below 4 GiB.  The step-0 pulls run two
-// iterations ahead of their use and are issued at the start of an iteration,
-// before its stores, in every iteration and for every lane (the row clamped
-// to the window), so that no path through the loop skips a load: the wait for
-// a set of pulls then covers only memory operations at least one iteration
-// old.  The loop is unrolled three times over three register sets, one per
-// iteration in flight.  Step 0 also runs on the rows of the padding
-// iterations past the window; those rows land in ring slots no live row
-// needs and are never read.
-template <typename S, int FM, bool SR, int NS, int NW, int RING, bool KEEP>
-__device__ __forceinline__ void strip_walk_fast(const KArgs<typename Codec<S>::R>& a,
-                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
-                                                S* __restrict__ dst, S* const (&keep)[2], const uint32_t (&key)[3],
-                                                int x0, int ys, int ye, S (&rg)[NS - 1][9][RING][64]) {
-  using R = typename Codec<S>::R;
-  const Geom& g = a.g;
-  const int lane = (int)threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int wx = x0 - (NS - 1) + lane;
-  const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
-  const __amdgpu_buffer_rsrc_t wr = rsrc(dst, g.lattice_bytes);
-  const int rlast = ye + NS - 2;  // last step-0 row of the window
-  const int nit = (ye - ys + 2 * (NS - 1) + NW - 1) / NW;
-  const int nit3 = (nit + 2) / 3 * 3;
-  auto fetch = [&](int it, R (&d)[9]) {
-    const int r = min(ys - (NS - 1) + it * NW + w, rlast);
-    const uint32_t off = (uint32_t)(r * g.pitch + wx) * (uint32_t)sizeof(S);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
-  };
-  auto body = [&](int it, const R (&dc)[9], R (&dn)[9]) {
-    fetch(it + 2, dn);
-    const int r0 = ys - (NS - 1) + it * NW + w;  // wavefront-uniform
-    {
-      const int gy = min(r0, rlast);
-      R Fx, Fy;
-      force_at<FM>(a, wx, gy, Fx, Fy);
-      R out[9];
-      collide_step<R, FM != 0>(rt, Fx, Fy, dc, out);
-      S o[9];
-      round_out<S, SR>(out, (uint32_t)(gy * g.nx + wx), key[0], o);
-      const int sl = ring_slot<RING>(r0);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) rg[0][k][sl][lane] = o[k];
-      if (KEEP && r0 >= ys && r0 < ye && lane >= NS - 1 && lane < 64 - (NS - 1))
-        store_kept<S>(g, keep[0], wx, r0, o);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 1; s < NS; ++s) {
-      const int r = r0 - s;
-      if (r >= ys - (NS - 1 - s) && r < ye + (NS - 1 - s) && lane >= s && lane < 64 - s) {
-        R d[9];
-        pull_ring<false, S, R, RING>(a, wx, r, rg[s - 1], lane, ring_slot<RING>(r - 1), ring_slot<RING>(r),
-                                     ring_slot<RING>(r + 1), d);
-        R Fx, Fy;
-        force_at<FM>(a, wx, r, Fx, Fy);
-        R out[9];
-        collide_step<R, FM != 0>(rt, Fx, Fy, d, out);
-        S o[9];
-        round_out<S, SR>(out, (uint32_t)(r * g.nx + wx), key[s], o);
-        if (s < NS - 1) {
-          const int sl = ring_slot<RING>(r);
-#pragma unroll
-          for (int k = 0; k < 9; ++k) rg[s < NS - 1 ? s : 0][k][sl][lane] = o[k];
-          if (KEEP && r >= ys && r < ye && lane >= NS - 1 && lane < 64 - (NS - 1))
-            store_kept<S>(g, keep[s < NS - 1 ? s : 0], wx, r, o);
-        } else {
-          const uint32_t off = (uint32_t)(r * g.pitch + wx) * (uint32_t)sizeof(S);
-#pragma unroll
-          for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(wr, off, g.st_soff[k], o[k]);
-        }
-      }
-      if (s < NS - 1) __syncthreads();
-    }
-  };
-  R p0[9], p1[9], p2[9];
-  fetch(0, p0);
-  __builtin_amdgcn_sched_barrier(0);  // keep the pulls of iteration 0 the older ones
-  fetch(1, p1);
-  for (int it = 0; it < nit3; it += 3) {
-    body(it, p0, p2);
-    body(it + 1, p1, p0);
-    body(it + 2, p2, p1);
-  }
-}
-
-// NS (2 or 3) fused steps per launch, strip tiling (see above); the grid has
-// st.strips * st.segs workgroups.  KEEP: the intermediate states n+1 (and
-// n+2) are also stored, to keep0 (and keep1).
-template <typename S, int FM, bool SR, int NS, int NW, int RING, bool KEEP>
-__global__ __launch_bounds__(64 * NW) void k_strip(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
-                                                   S* __restrict__ dst, S* keep0, S* keep1, uint32_t key_a,
-                                                   uint32_t key_b, uint32_t key_c) {
-  static_assert(NS == 2 || NS == 3, "two or three fused steps");
-  static_assert(RING >= (NS == 2 ? 2 * NW + 2 : NW + 2), "ring too short for the rows alive at once");
-  constexpr int TW = 64 - 2 * (NS - 1);
-  __shared__ S rg[NS - 1][9][RING][64];
-  const Geom& g = a.g;
-  const StripTiling& t = NS == 3 ? g.st3 : g.st2;
-  const auto rt = rates(a);
-  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  const int x0 = (tile % t.strips) * TW;
-  const int ys = (tile / t.strips) * t.len;
-  const int ye = min(ys + t.len, g.ny);
-  const uint32_t key[3] = {key_a, key_b, key_c};
-  S* const keep[2] = {keep0, keep1};
-  // interior: every window node lies in [1, n - 2] in both directions, so no
-  // link of any node the workgroup computes crosses a wall or wraps.
-  const bool interior = x0 - (NS - 1) >= 1 && x0 + 64 - NS <= g.nx - 2 && ys - (NS - 1) >= 1 &&
-                        ye + NS - 2 <= g.ny - 2;
-  if (interior && g.fast)  // workgroup-uniform: every wavefront meets the same barriers
-    strip_walk_fast<S, FM, SR, NS, NW, RING, KEEP>(a, rt, src, dst, keep, key, x0, ys, ye, rg);
-  else
-    strip_walk_edge<S, FM, SR, NS, NW, RING, KEEP>(a, rt, src, dst, keep, key, x0, ys, ye, rg);
 }
 
 // Initial state f-bar = f^eq - S/2 (transformed equilibrium with hF = -F/2).
@@ -1395,84 +1193,62 @@ hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t 
   }
 }
 
-template <bool SR, bool KEEP>
-static hipError_t launch_strip3_fm(const KArgs<float>& k, const void* src, void* dst, void* keep0, void* keep1,
-                                   uint32_t ka, uint32_t kb, uint32_t kc, hipStream_t st) {
-  constexpr int NW = kStripWaves, RING = kStripRing;
-  const StripTiling& t = k.g.st3;
-  if (t.len < 1 || t.strips < 1 || t.segs < 1 || (int64_t)t.len * t.segs < k.g.ny ||
-      (int64_t)t.strips * (64 - 2 * 2) < k.g.nx)
-    return hipErrorInvalidValue;
-  const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
-  const dim3 grid((unsigned)(t.strips * t.segs)), block(64 * NW);
-  using S = float;
-  S *k0 = (S*)keep0, *k1 = (S*)keep1;
-  if (fm == 0)
-    hipLaunchKernelGGL((k_strip<S, 0, SR, 3, NW, RING, KEEP>), grid, block, 0, st, k, (const S*)src, (S*)dst, k0, k1,
-                       ka, kb, kc);
-  else if (fm == 1)
-    hipLaunchKernelGGL((k_strip<S, 1, SR, 3, NW, RING, KEEP>), grid, block, 0, st, k, (const S*)src, (S*)dst, k0, k1,
-                       ka, kb, kc);
-  else
-    hipLaunchKernelGGL((k_strip<S, 2, SR, 3, NW, RING, KEEP>), grid, block, 0, st, k, (const S*)src, (S*)dst, k0, k1,
-                       ka, kb, kc);
-  return hipGetLastError();
-}
-
-template <typename S, int TY, int NT, bool U>
-static hipError_t launch_step4_fmu(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                                   uint32_t kb, uint32_t kc, uint32_t kd, hipStream_t st) {
+template <typename S, int TY, int NT, bool U, bool KEEP>
+static hipError_t launch_step4_fmu(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, void* k0,
+                                   void* k1, void* k2, uint32_t ka, uint32_t kb, uint32_t kc, uint32_t kd,
+                                   hipStream_t st) {
   const int fm = k.force ? 2 : ((k.fx != 0 || k.fy != 0) ? 1 : 0);
   const dim3 grid((unsigned)(k.g.t3_tiles_x * ((k.g.ny + TY - 1) / TY)));
   if (fm == 0)
-    hipLaunchKernelGGL((k_step4<S, 0, false, TY, NT, U>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
-                       kc, kd);
+    hipLaunchKernelGGL((k_step4<S, 0, false, TY, NT, U, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst,
+                       (S*)k0, (S*)k1, (S*)k2, ka, kb, kc, kd);
   else if (fm == 1)
-    hipLaunchKernelGGL((k_step4<S, 1, false, TY, NT, U>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
-                       kc, kd);
+    hipLaunchKernelGGL((k_step4<S, 1, false, TY, NT, U, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst,
+                       (S*)k0, (S*)k1, (S*)k2, ka, kb, kc, kd);
   else
-    hipLaunchKernelGGL((k_step4<S, 2, false, TY, NT, U>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst, ka, kb,
-                       kc, kd);
+    hipLaunchKernelGGL((k_step4<S, 2, false, TY, NT, U, KEEP>), grid, dim3(NT), 0, st, k, (const S*)src, (S*)dst,
+                       (S*)k0, (S*)k1, (S*)k2, ka, kb, kc, kd);
   return hipGetLastError();
 }
 
-template <typename S, int TY, int NT>
-static hipError_t launch_step4_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, uint32_t ka,
-                                  uint32_t kb, uint32_t kc, uint32_t kd, hipStream_t st) {
-  return unit678(k) ? launch_step4_fmu<S, TY, NT, true>(k, src, dst, ka, kb, kc, kd, st)
-                    : launch_step4_fmu<S, TY, NT, false>(k, src, dst, ka, kb, kc, kd, st);
+template <typename S, int TY, int NT, bool KEEP = false>
+static hipError_t launch_step4_fm(const KArgs<typename Codec<S>::R>& k, const void* src, void* dst, void* k0,
+                                  void* k1, void* k2, uint32_t ka, uint32_t kb, uint32_t kc, uint32_t kd,
+                                  hipStream_t st) {
+  return unit678(k) ? launch_step4_fmu<S, TY, NT, true, KEEP>(k, src, dst, k0, k1, k2, ka, kb, kc, kd, st)
+                    : launch_step4_fmu<S, TY, NT, false, KEEP>(k, src, dst, k0, k1, k2, ka, kb, kc, kd, st);
 }
 
 hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                         uint32_t key_c, uint32_t key_d, hipStream_t st) {
   switch (a.storage) {
     case 0:
-      return launch_step4_fm<double, kStep4TyF64, kStep4ThreadsF64>(a.d, src, dst, key_a, key_b, key_c, key_d, st);
+      return launch_step4_fm<double, kStep4TyF64, kStep4ThreadsF64>(a.d, src, dst, nullptr, nullptr, nullptr, key_a,
+                                                                    key_b, key_c, key_d, st);
     case 1:
       if (a.f.g.t4_ty == kStep4TyF32Small)
-        return launch_step4_fm<float, kStep4TyF32Small, kStep4ThreadsF32Small>(a.f, src, dst, key_a, key_b, key_c,
-                                                                               key_d, st);
+        return launch_step4_fm<float, kStep4TyF32Small, kStep4ThreadsF32Small>(a.f, src, dst, nullptr, nullptr,
+                                                                               nullptr, key_a, key_b, key_c, key_d,
+                                                                               st);
       if (a.f.g.t4_ty == kStep4TyF32Mid)
-        return launch_step4_fm<float, kStep4TyF32Mid, kStep4ThreadsF32Mid>(a.f, src, dst, key_a, key_b, key_c, key_d,
-                                                                           st);
-      return launch_step4_fm<float, kStep4TyF32, kStep4ThreadsF32>(a.f, src, dst, key_a, key_b, key_c, key_d, st);
+        return launch_step4_fm<float, kStep4TyF32Mid, kStep4ThreadsF32Mid>(a.f, src, dst, nullptr, nullptr, nullptr,
+                                                                           key_a, key_b, key_c, key_d, st);
+      return launch_step4_fm<float, kStep4TyF32, kStep4ThreadsF32>(a.f, src, dst, nullptr, nullptr, nullptr, key_a,
+                                                                   key_b, key_c, key_d, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_strip3_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* dst,
-                              uint32_t key_a, uint32_t key_b, uint32_t key_c, hipStream_t st) {
-  if (a.storage != 1 || !keep0 || !keep1) return hipErrorInvalidValue;
-  return launch_strip3_fm<false, true>(a.f, src, dst, keep0, keep1, key_a, key_b, key_c, st);
-}
-
-int strip3_resident() {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per, k_strip<float, 0, false, 3, kStripWaves, kStripRing, false>, 64 * kStripWaves, 0);
-  return e == hipSuccess ? cus * per : 0;
+hipError_t launch_step4_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* keep2, void* dst,
+                             uint32_t key_a, uint32_t key_b, uint32_t key_c, uint32_t key_d, hipStream_t st) {
+  if (a.storage != 1 || !keep0 || !keep1 || !keep2) return hipErrorInvalidValue;
+  if (a.f.g.t4_ty == kStep4TyF32Small)
+    return launch_step4_fm<float, kStep4TyF32Small, kStep4ThreadsF32Small, true>(a.f, src, dst, keep0, keep1, keep2,
+                                                                                 key_a, key_b, key_c, key_d, st);
+  if (a.f.g.t4_ty == kStep4TyF32Mid)
+    return launch_step4_fm<float, kStep4TyF32Mid, kStep4ThreadsF32Mid, true>(a.f, src, dst, keep0, keep1, keep2,
+                                                                             key_a, key_b, key_c, key_d, st);
+  return hipErrorInvalidValue;  // the 64 x 24 tiles (lattices above kStep4MidMaxNodes) take no kept states
 }
 
 hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t key, hipStream_t st) {

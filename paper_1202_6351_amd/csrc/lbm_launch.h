@@ -7,12 +7,6 @@
 
 namespace lbm {
 
-// Strip tiling of the fused kernels: strips of 64 - 2 (steps - 1) columns,
-// cut into segs segments of len rows (the last one may be shorter).
-struct StripTiling {
-  int32_t len, strips, segs;
-};
-
 // Lattice geometry and launch tiling.
 struct Geom {
   int32_t nx, ny;
@@ -34,7 +28,6 @@ struct Geom {
   int32_t t2_ty, t2_tiles_x, t2_tiles_y;
   int32_t t3_ty, t3_tiles_x, t3_tiles_y, t3_threads;
   int32_t t4_ty;  // four-step kernel tile height (FP32: by lattice size)
-  StripTiling st2, st3;
 };
 
 // Three-step kernel shapes: output tile 64 x TY, NT threads per workgroup
@@ -45,18 +38,6 @@ constexpr int kStep3TyF32 = 12, kStep3ThreadsF32 = 256;
 constexpr int kStep3TyF64 = 4, kStep3ThreadsF64 = 256;
 constexpr int kStep3TyF64Large = 10, kStep3ThreadsF64Large = 512;
 constexpr int64_t kStep3LargeMinNodes = 1 << 20;
-
-// Three-step strip kernel (FP32): wavefronts per workgroup, ring rows per
-// intermediate step, and its segment length: the launch is cut into about
-// kStripRounds waves of resident workgroups (segments per strip =
-// kStripRounds x resident workgroups / strips), segments at least
-// kStripMinLen rows.  The kernel serves the state-keeping recompute
-// (lbm_step_sequence) of FP32 lattices of up to kStripMaxNodes nodes; plain
-// stepping takes the four-step 64 x TY tiles at every size (measured on one
-// MI355X: ahead of the strips by 5 % at 512^2 and 15 % at 1024^2).
-constexpr int kStripWaves = 4, kStripRing = 6;
-constexpr int kStripRounds = 16, kStripMinLen = 8;
-constexpr int64_t kStripMaxNodes = (int64_t)1 << 20;
 
 // Step kernels write a lattice back through the caches (instead of
 // streaming it past them) when both lattices together take at most this many
@@ -127,19 +108,16 @@ hipError_t launch_step2(const KArgsAny& a, const void* src, void* dst, uint32_t 
 // calls.
 hipError_t launch_step3(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                         uint32_t key_c, hipStream_t st);
-// Strip-tiled three-step launch (FP32 only; the tiling is g.st3) that also
-// stores the intermediate states n+1 to keep0 and n+2 to keep1 (src, keep0,
-// keep1, dst pairwise distinct).  Same result as three launch_step calls
-// src -> keep0 -> keep1 -> dst.
-hipError_t launch_strip3_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* dst,
-                              uint32_t key_a, uint32_t key_b, uint32_t key_c, hipStream_t st);
-// Workgroups of the three-step strip kernel resident on the current device at
-// once (compute units x workgroups per unit); 0 if the device query fails.
-int strip3_resident();
 // Four steps in one launch (FP32, FP64): src (state n) -> dst (state n+4), keys of
 // steps n .. n+3.  Same result as four launch_step calls.
 hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t key_a, uint32_t key_b,
                         uint32_t key_c, uint32_t key_d, hipStream_t st);
+// The same, also storing the intermediate states n+1, n+2, n+3 to keep0,
+// keep1, keep2 (src, keep0..2, dst pairwise distinct): the same result as
+// four launch_step calls src -> keep0 -> keep1 -> keep2 -> dst.  FP32 on
+// lattices of up to kStep4MidMaxNodes nodes only (else hipErrorInvalidValue).
+hipError_t launch_step4_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* keep2, void* dst,
+                             uint32_t key_a, uint32_t key_b, uint32_t key_c, uint32_t key_d, hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
                        hipStream_t st);
 hipError_t launch_set(const KArgsAny& a, const void* f, void* dst, hipStream_t st);

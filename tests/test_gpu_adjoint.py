@@ -391,24 +391,26 @@ def test_handle_on_another_stream():
     assert lat.diagnostics()[0] > 0  # the original's first diagnostics call makes its scratch
 
 
-@pytest.mark.parametrize("pattern", ["pingpong", "cycle3", "cycle4"])
+@pytest.mark.parametrize("pattern", ["pingpong", "cycle3", "cycle4", "cycle5"])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_step_sequence_with_reused_buffers(pattern, storage):
     """lbm_step_sequence may reuse a buffer once its state has been read.  In
-    FP32 lattices of up to 2^20 nodes the library fuses groups of three steps
-    (storing the intermediate states) only when the group's four buffers are
-    distinct and falls back
-    to single steps otherwise: ping-pong buffers never fuse, a cycle of
-    three fuses once, a cycle of four twice.  Every buffer ends holding the
-    state last written into it, as with single steps."""
+    FP32 lattices of up to 1.2 M nodes the library fuses groups of four steps
+    (storing the three intermediate states) only when the group's five
+    buffers are distinct and falls back to single steps otherwise: ping-pong
+    buffers and a cycle of three never fuse, a cycle of four fuses once (the
+    next group's input is its own output buffer), a cycle of five twice.
+    Every buffer ends holding the state last written into it, as with single
+    steps."""
     nx, ny = 130, 70
     bc, wu = BCS[2]
     lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=14), storage=storage, tau=0.65, bc=bc, wall_u=wu)
     lat.set_populations(W.random_populations(nx, ny, seed=15, amp=0.05))
     src = lat.snapshot()
     n = 8
-    bufs = [lat.new_lattice() for _ in range(4)]
-    idx = {"pingpong": [0, 1] * 4, "cycle3": [0, 1, 2] * 3, "cycle4": [0, 1, 2, 3] * 2}[pattern][:n]
+    bufs = [lat.new_lattice() for _ in range(5)]
+    idx = {"pingpong": [0, 1] * 4, "cycle3": [0, 1, 2] * 3, "cycle4": [0, 1, 2, 3] * 2,
+           "cycle5": [0, 1, 2, 3, 4] * 2}[pattern][:n]
     lat.step_sequence(src, [bufs[j] for j in idx])
     prev, ref = src, []
     for _ in range(n):
