@@ -351,8 +351,9 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
   }
   // FP32 lattices of up to kStep4MidMaxNodes nodes run groups of four steps
   // as one four-step launch that also stores the three intermediate states,
-  // as long as the group's five buffers are distinct; the rest runs as
-  // single steps.
+  // as long as the group's five buffers are distinct, and a remainder of
+  // three or two steps as one launch of that form cut short; the rest runs
+  // as single steps.
   const uint32_t key = step_key(c->p, c->t);
   int64_t i = 0;
   const bool tiles4 = c->p.storage == LBM_FP32 && (int64_t)c->p.nx * c->p.ny <= lbm::kStep4MidMaxNodes;
@@ -367,6 +368,21 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
     lbm_status s = dev_err(c, lbm::launch_step4_keep(c->args, in, k0, k1, k2, out, key, key, key, key, c->stream),
                            "four-step kernel");
     if (s != LBM_OK) return s;
+  }
+  if (tiles4 && (n - i == 3 || n - i == 2)) {
+    const int r = (int)(n - i);
+    const void* in = i == 0 ? src : states[i - 1];
+    void* k0 = states[i];
+    void* k1 = states[i + 1];
+    void* k2 = r == 3 ? states[i + 2] : nullptr;
+    const bool distinct = in != k1 && k0 != k1 && (!k2 || (in != k2 && k0 != k2 && k1 != k2));  // in != k0 checked
+    if (distinct) {
+      lbm_status s = dev_err(c, lbm::launch_step4_keep(c->args, in, k0, k1, k2, nullptr, key, key, key, key,
+                                                       c->stream),
+                             "four-step kernel");
+      if (s != LBM_OK) return s;
+      i = n;
+    }
   }
   for (; i < n; ++i) {
     lbm_status s = dev_err(c, lbm::launch_step(c->args, i == 0 ? src : states[i - 1], states[i], key, c->stream),

@@ -700,7 +700,9 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
 // KEEP: the intermediate states n+1, n+2, n+3 of the tile's nodes are also
 // stored to keep0, keep1, keep2 (the state-keeping recompute); the later
 // stages then issue no load after those stores, which would otherwise wait
-// for them (loads and stores share one completion counter).
+// for them (loads and stores share one completion counter).  A KEEP launch
+// with dst null stops after keep2, and with keep2 (and dst) null after
+// keep1: three or two kept steps (the decision is uniform over the grid).
 template <typename S, int FM, bool SR, int TY, int NT, bool U, bool KEEP>
 __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
                                                S* __restrict__ dst, S* __restrict__ keep0, S* __restrict__ keep1,
@@ -721,11 +723,15 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
   __syncthreads();
   if (interior) {  // workgroup-uniform: every thread meets the same barriers
     stage_in_lds<false, S, FM, SR, EH, EW, H, 2, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_b, mid, fw, keep1);
+    if (KEEP && !keep2) return;
     stage_in_lds<false, S, FM, SR, EH, EW, H, 1, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_c, mid, fw, keep2);
+    if (KEEP && !dst) return;
     stage_to_hbm<false, S, FM, SR, TY, EH, EW, H, NT, U, FW>(a, rt, x0, y0, key_d, mid, dst, fw);
   } else {
     stage_in_lds<true, S, FM, SR, EH, EW, H, 2, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_b, mid, fw, keep1);
+    if (KEEP && !keep2) return;
     stage_in_lds<true, S, FM, SR, EH, EW, H, 1, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_c, mid, fw, keep2);
+    if (KEEP && !dst) return;
     stage_to_hbm<true, S, FM, SR, TY, EH, EW, H, NT, U, FW>(a, rt, x0, y0, key_d, mid, dst, fw);
   }
 }
@@ -1241,7 +1247,7 @@ hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t 
 
 hipError_t launch_step4_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* keep2, void* dst,
                              uint32_t key_a, uint32_t key_b, uint32_t key_c, uint32_t key_d, hipStream_t st) {
-  if (a.storage != 1 || !keep0 || !keep1 || !keep2) return hipErrorInvalidValue;
+  if (a.storage != 1 || !keep0 || !keep1 || (!keep2 && dst)) return hipErrorInvalidValue;
   if (a.f.g.t4_ty == kStep4TyF32Small)
     return launch_step4_fm<float, kStep4TyF32Small, kStep4ThreadsF32Small, true>(a.f, src, dst, keep0, keep1, keep2,
                                                                                  key_a, key_b, key_c, key_d, st);
