@@ -54,6 +54,23 @@ def _backward_streams(dev: torch.device):
     return _BACKWARD_STREAMS[key]
 
 
+def _backward_setup(lat: Lattice, width: int, nseg: int):
+    """What the backward needs besides the forward's results: the two
+    streams and a library context on each, the cotangent pair, the force
+    gradient, the initial-velocity gradient and the second set of segment
+    buffers.  Made at the end of the forward when a gradient is wanted, while
+    the GPU still runs the forward's steps, so that the host work of the
+    backward's start is hidden."""
+    p, dev, real = lat.params, lat.device, lat.real
+    main, side = _backward_streams(dev)
+    set1_base, set1 = _lattice_set(lat, width if nseg > 1 else 0)
+    return dict(main=main, side=side, adj=lat.on_stream(main), rec=lat.on_stream(side),
+                mu=lat.new_cotangent(), mu2=lat.new_cotangent(),
+                grad_force=torch.zeros((2, p.ny, p.nx), dtype=real, device=dev),
+                g_u0=torch.empty((2, p.ny, p.nx), dtype=real, device=dev),
+                set1_base=set1_base, set1=set1)
+
+
 class Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, force: torch.Tensor, u0: torch.Tensor, params: Params, steps: int,
@@ -95,29 +112,27 @@ class Rollout(torch.autograd.Function):
         ctx.bases = (snap_base, keep_base)
         ctx.keep = keep
         ctx.init_fields = (rho, ux0, uy0)
+        ctx.prep = (_backward_setup(lat, max(min(every, steps) - 1, 0), nseg)
+                    if any(ctx.needs_input_grad[:2]) else None)
         return m["rho"], torch.stack([m["ux"], m["uy"]])
 
     @staticmethod
     def backward(ctx, g_rho, g_u):
         lat: Lattice = ctx.lat
         steps, every = ctx.steps, ctx.every
-        p = lat.params
         dev, real = lat.device, lat.real
-        grad_force = torch.zeros((2, p.ny, p.nx), dtype=real, device=dev)
-        g_rho = None if g_rho is None else g_rho.to(real).contiguous()
-        g_ux = None if g_u is None else g_u[0].to(real).contiguous()
-        g_uy = None if g_u is None else g_u[1].to(real).contiguous()
-        mu, mu2 = lat.new_cotangent(), lat.new_cotangent()
         snaps = ctx.snaps
         nseg = len(snaps)
         seg_len = [max(min(every, steps - s * every), 0) for s in range(nseg)]
         width = max(min(every, max(steps, 0)) - 1, 0)
+        prep = ctx.prep if ctx.prep is not None else _backward_setup(lat, width, nseg)
+        g_rho = None if g_rho is None else g_rho.to(real).contiguous()
+        g_ux = None if g_u is None else g_u[0].to(real).contiguous()
+        g_uy = None if g_u is None else g_u[1].to(real).contiguous()
+        mu, mu2, grad_force, g_u0 = prep["mu"], prep["mu2"], prep["grad_force"], prep["g_u0"]
         # set 0: the forward's kept states of the last segment; set 1: new
-        set1_base, set1 = _lattice_set(lat, width if nseg > 1 else 0)
-        sets = [ctx.keep, set1]
+        sets = [ctx.keep, prep["set1"]]
         rho, ux0, uy0 = ctx.init_fields
-        g_ux0 = torch.empty_like(ux0, dtype=real)
-        g_uy0 = torch.empty_like(uy0, dtype=real)
         # Adjoint calls run on `main`, recomputes on `side`, each through a
         # context of its own over the forward's buffers and force field.  A
         # segment of n steps needs its snapshot and the n - 1 states after
@@ -126,17 +141,15 @@ class Rollout(torch.autograd.Function):
         # forward's stream (snapshots, final state) and the caller's (the
         # loss cotangents and every buffer allocated above).
         caller = torch.cuda.current_stream(dev)
-        main, side = _backward_streams(dev)
+        main, side, adj, rec = prep["main"], prep["side"], prep["adj"], prep["rec"]
         for st in (main, side):
             st.wait_stream(lat.stream)
             st.wait_stream(caller)
-        for t in (*ctx.bases, set1_base, lat.force, lat.current, grad_force, mu, mu2, g_rho, g_ux, g_uy,
-                  g_ux0, g_uy0, rho, ux0, uy0):
+        for t in (*ctx.bases, prep["set1_base"], lat.force, lat.current, grad_force, mu, mu2, g_rho, g_ux, g_uy,
+                  g_u0, rho, ux0, uy0):
             if t is not None:
                 t.record_stream(side)
                 t.record_stream(main)
-        adj = lat.on_stream(main)
-        rec = lat.on_stream(side)
         ready = [torch.cuda.Event(), torch.cuda.Event()]
         free = [None, None]
 
@@ -166,10 +179,10 @@ class Rollout(torch.autograd.Function):
                 free[b] = torch.cuda.Event()
                 free[b].record(main)
             main.wait_stream(side)
-            adj.adjoint_init(rho, ux0, uy0, mu, None, g_ux0, g_uy0, grad_force)
+            adj.adjoint_init(rho, ux0, uy0, mu, None, g_u0[0], g_u0[1], grad_force)
         caller.wait_stream(main)
-        ctx.lat = ctx.snaps = ctx.keep = ctx.bases = None
-        return grad_force, torch.stack([g_ux0, g_uy0]), None, None, None, None
+        ctx.lat = ctx.snaps = ctx.keep = ctx.bases = ctx.prep = None
+        return grad_force, g_u0, None, None, None, None
 
 
 def rollout(params: Params, force: torch.Tensor, u0: torch.Tensor, steps: int,
