@@ -915,6 +915,109 @@ __global__ __launch_bounds__(256) void k_adjoint_step(KArgs<typename Codec<S>::R
   }
 }
 
+// Pull and its transpose for a node whose links all stay inside the domain
+// (no wall, no wrap): plane A at (x - e_x, y - e_y).
+template <typename S, typename R>
+__device__ __forceinline__ void gather_inner(const Geom& g, const S* __restrict__ src, int x, int y, R d[9]) {
+  const int64_t c = (int64_t)y * g.pitch + x;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(src[(int64_t)k * g.plane + c - EY[k] * g.pitch - EX[k]]);
+}
+
+template <typename R>
+__device__ __forceinline__ void scatter_inner(const Geom& g, R* __restrict__ dst, int x, int y, const R v[9]) {
+  const int64_t c = (int64_t)y * g.pitch + x;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dst[(int64_t)k * g.plane + c - EY[k] * g.pitch - EX[k]] = v[k];
+}
+
+// One workgroup's two adjoint steps (see k_adjoint_step2).  WALLS = false:
+// every node the tile touches and its neighbours lie inside the domain, so
+// the pulls, the reverse streaming and the window lookups need no wall or
+// wrap handling.
+template <bool WALLS, typename S, int TY>
+__device__ __forceinline__ void adjoint_pair_tile(const KArgs<typename Codec<S>::R>& a, int x0, int y0,
+                                                  const S* __restrict__ prev_a, const S* __restrict__ prev_b,
+                                                  const typename Codec<S>::R* __restrict__ mu_in,
+                                                  typename Codec<S>::R* __restrict__ mu_out,
+                                                  typename Codec<S>::R* __restrict__ grad_force,
+                                                  typename Codec<S>::R (&mid)[9][TY + 4][68],
+                                                  typename Codec<S>::R (&aF1)[2][TY][64]) {
+  using R = typename Codec<S>::R;
+  constexpr int H = 2, EW = 64 + 2 * H, EH = TY + 2 * H;
+  const Geom& g = a.g;
+  const Rates<R> r = rates(a);
+  const int wx0 = x0 - H, wy0 = y0 - H;
+  // ---- stage 1: adjoint of step n on the tile and a one-node ring
+  constexpr int RW = EW - 2, RH = EH - 2;
+  for (int i = (int)threadIdx.x; i < RW * RH; i += 256) {
+    const int cx = 1 + i % RW, cy = 1 + i / RW;
+    int gx = wx0 + cx, gy = wy0 + cy;
+    if (WALLS && !window_node(g, wx0 + cx, wy0 + cy, gx, gy)) continue;
+    R d[9];
+    if constexpr (WALLS) gather<S, R>(g, a.wadd, prev_a, gx, gy, d);
+    else gather_inner<S, R>(g, prev_a, gx, gy, d);
+    R Fx, Fy;
+    node_force(a, gx, gy, Fx, Fy);
+    R out[9];
+    NodeFwd<R> st;
+    collide(r, Fx, Fy, d, out, st);
+    const int64_t c = (int64_t)gy * g.pitch + gx;
+    R mu[9], nu[9], ax = R(0), ay = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * g.plane + c];
+    collide_T(r, st, mu, nu, ax, ay);
+    if constexpr (WALLS) {
+      const Edges e = edges(g, gx, gy);
+#define LBM_SCATTER_WIN(A)                                                        \
+      {                                                                           \
+        constexpr int sx = EX[A], sy = EY[A];                                     \
+        const bool hx = (sx == 1 && e.wxl) || (sx == -1 && e.wxh);                \
+        const bool hy = (sy == 1 && e.wyl) || (sy == -1 && e.wyh);                \
+        if (hx || hy) mid[OPP[A]][cy][cx] = nu[A];                                \
+        else mid[A][cy - sy][cx - sx] = nu[A];                                    \
+      }
+      LBM_SCATTER_WIN(0) LBM_SCATTER_WIN(1) LBM_SCATTER_WIN(2) LBM_SCATTER_WIN(3) LBM_SCATTER_WIN(4)
+      LBM_SCATTER_WIN(5) LBM_SCATTER_WIN(6) LBM_SCATTER_WIN(7) LBM_SCATTER_WIN(8)
+#undef LBM_SCATTER_WIN
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) mid[k][cy - EY[k]][cx - EX[k]] = nu[k];
+    }
+    if (cx >= H && cx < H + 64 && cy >= H && cy < H + TY) {
+      aF1[0][cy - H][cx - H] = ax;
+      aF1[1][cy - H][cx - H] = ay;
+    }
+  }
+  __syncthreads();
+  // ---- stage 2: adjoint of step n-1 on the tile
+  const int lx = (int)threadIdx.x & 63;
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += 4) {
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= g.nx || gy >= g.ny) continue;
+    R d[9];
+    if constexpr (WALLS) gather<S, R>(g, a.wadd, prev_b, gx, gy, d);
+    else gather_inner<S, R>(g, prev_b, gx, gy, d);
+    R Fx, Fy;
+    node_force(a, gx, gy, Fx, Fy);
+    R out[9];
+    NodeFwd<R> st;
+    collide(r, Fx, Fy, d, out, st);
+    R mu[9], nu[9], ax = R(0), ay = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mu[k] = mid[k][ly + H][lx + H];
+    collide_T(r, st, mu, nu, ax, ay);
+    if constexpr (WALLS) scatter<R, R>(g, a.wadd, mu_out, gx, gy, nu, false);
+    else scatter_inner<R>(g, mu_out, gx, gy, nu);
+    if (grad_force) {
+      const int64_t cf = (int64_t)gy * g.nx + gx;
+      grad_force[cf] = (grad_force[cf] + aF1[0][ly][lx]) + ax;
+      const int64_t cg = (int64_t)g.nx * g.ny + cf;
+      grad_force[cg] = (grad_force[cg] + aF1[1][ly][lx]) + ay;
+    }
+  }
+}
+
 // Two adjoint steps per launch, newest first: the cotangent mu_in of state
 // n+1 goes back through step n (state n in prev_a) and then step n-1 (state
 // n-1 in prev_b) to the cotangent mu_out of state n-1.  A workgroup owns a
@@ -933,74 +1036,18 @@ __global__ __launch_bounds__(256) void k_adjoint_step2(KArgs<typename Codec<S>::
                                                        typename Codec<S>::R* __restrict__ mu_out,
                                                        typename Codec<S>::R* __restrict__ grad_force) {
   using R = typename Codec<S>::R;
-  constexpr int H = 2, EW = 64 + 2 * H, EH = TY + 2 * H;
-  __shared__ R mid[9][EH][EW];      // cotangent of state n on the window
+  __shared__ R mid[9][TY + 4][68];  // cotangent of state n on the window (two-node ring)
   __shared__ R aF1[2][TY][64];      // stage 1 force cotangents of the tile
   const Geom& g = a.g;
-  const Rates<R> r = rates(a);
   const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const int x0 = (tile % g.t2_tiles_x) * 64, y0 = (tile / g.t2_tiles_x) * TY;
-  const int wx0 = x0 - H, wy0 = y0 - H;
-  // ---- stage 1: adjoint of step n on the tile and a one-node ring
-  constexpr int RW = EW - 2, RH = EH - 2;
-  for (int i = (int)threadIdx.x; i < RW * RH; i += 256) {
-    const int cx = 1 + i % RW, cy = 1 + i / RW;
-    int gx, gy;
-    if (!window_node(g, wx0 + cx, wy0 + cy, gx, gy)) continue;
-    R d[9];
-    gather<S, R>(g, a.wadd, prev_a, gx, gy, d);
-    R Fx, Fy;
-    node_force(a, gx, gy, Fx, Fy);
-    R out[9];
-    NodeFwd<R> st;
-    collide(r, Fx, Fy, d, out, st);
-    const int64_t c = (int64_t)gy * g.pitch + gx;
-    R mu[9], nu[9], ax = R(0), ay = R(0);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * g.plane + c];
-    collide_T(r, st, mu, nu, ax, ay);
-    const Edges e = edges(g, gx, gy);
-#define LBM_SCATTER_WIN(A)                                                        \
-    {                                                                             \
-      constexpr int sx = EX[A], sy = EY[A];                                       \
-      const bool hx = (sx == 1 && e.wxl) || (sx == -1 && e.wxh);                  \
-      const bool hy = (sy == 1 && e.wyl) || (sy == -1 && e.wyh);                  \
-      if (hx || hy) mid[OPP[A]][cy][cx] = nu[A];                                  \
-      else mid[A][cy - sy][cx - sx] = nu[A];                                      \
-    }
-    LBM_SCATTER_WIN(0) LBM_SCATTER_WIN(1) LBM_SCATTER_WIN(2) LBM_SCATTER_WIN(3) LBM_SCATTER_WIN(4)
-    LBM_SCATTER_WIN(5) LBM_SCATTER_WIN(6) LBM_SCATTER_WIN(7) LBM_SCATTER_WIN(8)
-#undef LBM_SCATTER_WIN
-    if (cx >= H && cx < H + 64 && cy >= H && cy < H + TY) {
-      aF1[0][cy - H][cx - H] = ax;
-      aF1[1][cy - H][cx - H] = ay;
-    }
-  }
-  __syncthreads();
-  // ---- stage 2: adjoint of step n-1 on the tile
-  const int lx = (int)threadIdx.x & 63;
-  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += 4) {
-    const int gx = x0 + lx, gy = y0 + ly;
-    if (gx >= g.nx || gy >= g.ny) continue;
-    R d[9];
-    gather<S, R>(g, a.wadd, prev_b, gx, gy, d);
-    R Fx, Fy;
-    node_force(a, gx, gy, Fx, Fy);
-    R out[9];
-    NodeFwd<R> st;
-    collide(r, Fx, Fy, d, out, st);
-    R mu[9], nu[9], ax = R(0), ay = R(0);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) mu[k] = mid[k][ly + H][lx + H];
-    collide_T(r, st, mu, nu, ax, ay);
-    scatter<R, R>(g, a.wadd, mu_out, gx, gy, nu, false);
-    if (grad_force) {
-      const int64_t cf = (int64_t)gy * g.nx + gx;
-      grad_force[cf] = (grad_force[cf] + aF1[0][ly][lx]) + ax;
-      const int64_t cg = (int64_t)g.nx * g.ny + cf;
-      grad_force[cg] = (grad_force[cg] + aF1[1][ly][lx]) + ay;
-    }
-  }
+  // stage 1 nodes span [x0 - 1, x0 + 64] x [y0 - 1, y0 + TY]; none on the
+  // domain's edge rows or columns means no wall link and no wrap anywhere
+  const bool inner = x0 >= 2 && x0 + 66 <= g.nx && y0 >= 2 && y0 + TY + 2 <= g.ny;
+  if (inner)  // workgroup-uniform
+    adjoint_pair_tile<false, S, TY>(a, x0, y0, prev_a, prev_b, mu_in, mu_out, grad_force, mid, aF1);
+  else
+    adjoint_pair_tile<true, S, TY>(a, x0, y0, prev_a, prev_b, mu_in, mu_out, grad_force, mid, aF1);
 }
 
 // Adjoint of the macroscopic map rho, u at lattice lat.
