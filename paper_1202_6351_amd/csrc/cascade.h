@@ -175,12 +175,14 @@ LBM_HD void equilibrium_cm_T(R r0, R ux, R uy, const R aCs[3][3], R& adrho,
   adrho += aCs[0][0] + R(1.0 / 3.0) * (aCs[2][0] + aCs[0][2]) + R(1.0 / 9.0) * aCs[2][2];
   ahFx += aCs[1][0];
   ahFy += aCs[0][1];
-  aux += r0 * aCs[1][0] - R(2) * r0 * ux * aCs[2][0] - r0 * uy * aCs[1][1] +
-         R(2) * r0 * ux * uy * aCs[2][1] + r0 * (R(1.0 / 3.0) + uy2) * aCs[1][2] -
-         r0 * (R(2.0 / 3.0) * ux + R(2) * ux * uy2) * aCs[2][2];
-  auy += r0 * aCs[0][1] - R(2) * r0 * uy * aCs[0][2] - r0 * ux * aCs[1][1] +
-         r0 * (R(1.0 / 3.0) + ux2) * aCs[2][1] + R(2) * r0 * ux * uy * aCs[1][2] -
-         r0 * (R(2.0 / 3.0) * uy + R(2) * uy * ux2) * aCs[2][2];
+  // d/du_x of the entries, the terms that carry a factor u_x gathered in gx
+  // (and likewise for u_y):
+  //   d/du_x = r0 [aCs10 - u_y aCs11 + (1/3 + u_y^2) aCs12
+  //                + u_x (2 (u_y aCs21 - aCs20) - (2/3 + 2 u_y^2) aCs22)]
+  const R gx = fmad(-fmad(R(2), uy2, R(2.0 / 3.0)), aCs[2][2], R(2) * fmad(uy, aCs[2][1], -aCs[2][0]));
+  const R gy = fmad(-fmad(R(2), ux2, R(2.0 / 3.0)), aCs[2][2], R(2) * fmad(ux, aCs[1][2], -aCs[0][2]));
+  aux = fmad(r0, fmad(ux, gx, fmad(-uy, aCs[1][1], fmad(R(1.0 / 3.0) + uy2, aCs[1][2], aCs[1][0]))), aux);
+  auy = fmad(r0, fmad(uy, gy, fmad(-ux, aCs[1][1], fmad(R(1.0 / 3.0) + ux2, aCs[2][1], aCs[0][1]))), auy);
 }
 
 // Collision increment of the central moments, Delta C = C* - C:
@@ -216,8 +218,8 @@ LBM_HD void relax_delta_T(const Rates<R>& r, R ux, R uy, const R aD[3][3],
                                               R& aFy) {
   aFx += aD[1][0];
   aFy += aD[0][1];
-  const R as = r.w3 * R(0.5) * (aD[2][0] + aD[0][2]);  // cotangent of the s target
-  const R ad = r.w4 * R(0.5) * (aD[2][0] - aD[0][2]);  // cotangent of the d target
+  const R as = r.hw3 * (aD[2][0] + aD[0][2]);  // cotangent of the s target
+  const R ad = r.hw4 * (aD[2][0] - aD[0][2]);  // cotangent of the d target
   R aE[3][3];
   aE[0][0] = R(0);
   aE[1][0] = R(0);
