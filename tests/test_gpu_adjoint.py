@@ -465,19 +465,23 @@ def test_rollout_forward_same_with_and_without_gradient(storage, T, every):
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-def test_step_sequence_large_shape(storage):
-    """lbm_step_sequence on 1030 x 1030 (above 2^20 nodes, where every
-    precision runs it as single steps), walls and lid, force field: seven
-    kept states equal seven lbm_step_between calls bit for bit."""
+@pytest.mark.parametrize("bci", [0, 2])
+@pytest.mark.parametrize("n", [6, 7])
+def test_step_sequence_large_shape(storage, bci, n):
+    """lbm_step_sequence on 1030 x 1030 (FP32 takes its 64 x 12 four-step
+    tiles that keep their states there: a group of four, then one launch cut
+    short after two or three steps; FP64 runs single steps), periodic or
+    walls and lid, force field: the kept states equal as many
+    lbm_step_between calls bit for bit."""
     nx = ny = 1030
-    bc, wu = BCS[2]
+    bc, wu = BCS[bci]
     lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=12), storage=storage, tau=0.6, bc=bc, wall_u=wu)
     lat.set_populations(W.random_populations(nx, ny, seed=13, amp=0.05))
     src = lat.snapshot()
-    seq = [lat.new_lattice() for _ in range(7)]
+    seq = [lat.new_lattice() for _ in range(n)]
     lat.step_sequence(src, seq)
     prev = src
-    for i in range(7):
+    for i in range(n):
         one = _step(lat, prev)
         assert torch.equal(one, seq[i]), i
         prev = one
