@@ -303,6 +303,15 @@ LBM_HD void populations_T(R ux, R uy, const R Cs[3][3], const R Y[3][3],
     ax_unc_T(uy, Cs[m][0], Cs[m][1], aY[m][0], aY[m][1], aY[m][2], aCs[m][0], aCs[m][1], aCs[m][2], auy);
 }
 
+// Reciprocal: IEEE division in double; for float the hardware estimate
+// refined by one Newton step (error below 1 ulp, a few instructions instead
+// of the correctly rounded division sequence).
+LBM_HD double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return r * __builtin_fmaf(-x, r, 2.0f);
+}
+
 // Hydrodynamic fields from the raw moments of d (Sec. II): rho = rho0 +
 // M_00, u = (M_10 + F_x/2, M_01 + F_y/2)/rho (the rest part has no momentum).
 template <typename R>
@@ -320,7 +329,11 @@ template <typename R>
 LBM_HD void collide(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9],
                                         NodeFwd<R>& s) {
   raw_moments(d, s.M);
-  node_fields(r, s.M, Fx, Fy, s.drho, s.inv_rho, s.ux, s.uy);
+  // the fields of node_fields, with 1/rho as in the step kernels' collision
+  s.drho = s.M[0][0];
+  s.inv_rho = recip(r.rho0 + s.drho);
+  s.ux = (s.M[1][0] + R(0.5) * Fx) * s.inv_rho;
+  s.uy = (s.M[0][1] + R(0.5) * Fy) * s.inv_rho;
   R C[3][3];
   central(s.ux, s.uy, s.M, s.X, C);
   relax_delta(r, s.drho, s.ux, s.uy, Fx, Fy, C, s.D);
@@ -368,15 +381,6 @@ LBM_HD void collide_T(const Rates<R>& r, const NodeFwd<R>& s, const R aout[9],
     ad[DIR[J][1]] = aout[DIR[J][1]] + a1;
     ad[DIR[J][2]] = aout[DIR[J][2]] + a2;
   }
-}
-
-// Reciprocal: IEEE division in double; for float the hardware estimate
-// refined by one Newton step (error below 1 ulp, a few instructions instead
-// of the correctly rounded division sequence).
-LBM_HD double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float recip(float x) {
-  const float r = __builtin_amdgcn_rcpf(x);
-  return r * __builtin_fmaf(-x, r, 2.0f);
 }
 
 // The collision of the step kernels: the same function as collide(), in the
