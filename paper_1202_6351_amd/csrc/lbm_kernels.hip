@@ -883,38 +883,6 @@ __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ p
   }
 }
 
-// Adjoint of one step: mu_out = J^T mu_in, grad_force += dL/dF.
-template <typename S>
-__global__ __launch_bounds__(256) void k_adjoint_step(KArgs<typename Codec<S>::R> a, const S* __restrict__ prev,
-                                                      const typename Codec<S>::R* __restrict__ mu_in,
-                                                      typename Codec<S>::R* __restrict__ mu_out,
-                                                      typename Codec<S>::R* __restrict__ grad_force) {
-  using R = typename Codec<S>::R;
-  const NodePos p = node_pos(a.g);
-  if (!p.valid) return;
-  R d[9];
-  gather<S, R>(a.g, a.wadd, prev, p.x, p.y, d);
-  R Fx, Fy;
-  node_force(a, p.x, p.y, Fx, Fy);
-  const Rates<R> r = rates(a);
-  R out[9];
-  NodeFwd<R> s;
-  collide(r, Fx, Fy, d, out, s);
-  const int64_t c = (int64_t)p.y * a.g.pitch + p.x;
-  R mu[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * a.g.plane + c];
-  R nu[9], aFx = R(0), aFy = R(0);
-  collide_T(r, s, mu, nu, aFx, aFy);
-  // Reverse streaming: the transpose of the gather permutation.
-  scatter<R, R>(a.g, a.wadd, mu_out, p.x, p.y, nu, false);
-  if (grad_force) {
-    const int64_t cf = (int64_t)p.y * a.g.nx + p.x;
-    grad_force[cf] += aFx;
-    grad_force[(int64_t)a.g.nx * a.g.ny + cf] += aFy;
-  }
-}
-
 // Pull and its transpose for a node whose links all stay inside the domain
 // (no wall, no wrap): plane A at (x - e_x, y - e_y).
 template <typename S, typename R>
@@ -929,6 +897,43 @@ __device__ __forceinline__ void scatter_inner(const Geom& g, R* __restrict__ dst
   const int64_t c = (int64_t)y * g.pitch + x;
 #pragma unroll
   for (int k = 0; k < 9; ++k) dst[(int64_t)k * g.plane + c - EY[k] * g.pitch - EX[k]] = v[k];
+}
+
+// Adjoint of one step: mu_out = J^T mu_in, grad_force += dL/dF.
+template <typename S>
+__global__ __launch_bounds__(256) void k_adjoint_step(KArgs<typename Codec<S>::R> a, const S* __restrict__ prev,
+                                                      const typename Codec<S>::R* __restrict__ mu_in,
+                                                      typename Codec<S>::R* __restrict__ mu_out,
+                                                      typename Codec<S>::R* __restrict__ grad_force) {
+  using R = typename Codec<S>::R;
+  const NodePos p = node_pos(a.g);
+  if (!p.valid) return;
+  // a node off the domain's edge rows and columns has no wall link and no
+  // wrap: plain offsets (only edge wavefronts diverge)
+  const bool inner = p.x >= 1 && p.x <= a.g.nx - 2 && p.y >= 1 && p.y <= a.g.ny - 2;
+  R d[9];
+  if (inner) gather_inner<S, R>(a.g, prev, p.x, p.y, d);
+  else gather<S, R>(a.g, a.wadd, prev, p.x, p.y, d);
+  R Fx, Fy;
+  node_force(a, p.x, p.y, Fx, Fy);
+  const Rates<R> r = rates(a);
+  R out[9];
+  NodeFwd<R> s;
+  collide(r, Fx, Fy, d, out, s);
+  const int64_t c = (int64_t)p.y * a.g.pitch + p.x;
+  R mu[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * a.g.plane + c];
+  R nu[9], aFx = R(0), aFy = R(0);
+  collide_T(r, s, mu, nu, aFx, aFy);
+  // Reverse streaming: the transpose of the gather permutation.
+  if (inner) scatter_inner<R>(a.g, mu_out, p.x, p.y, nu);
+  else scatter<R, R>(a.g, a.wadd, mu_out, p.x, p.y, nu, false);
+  if (grad_force) {
+    const int64_t cf = (int64_t)p.y * a.g.nx + p.x;
+    grad_force[cf] += aFx;
+    grad_force[(int64_t)a.g.nx * a.g.ny + cf] += aFy;
+  }
 }
 
 // One workgroup's two adjoint steps (see k_adjoint_step2).  WALLS = false:
