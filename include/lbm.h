@@ -21,8 +21,9 @@
  * Errors.  Every call returns an lbm_status and never aborts or throws.
  *   LBM_EINVAL: bad argument (message in lbm_last_error); nothing was
  *   launched.  LBM_EDEVICE: a HIP call or launch failed.  LBM_ESTATE: call
- *   out of order.  LBM_EUNSUPPORTED: valid request the storage mode does not
- *   support (the adjoint with FP16/BF16 storage).  LBM_EUNSTABLE: the
+ *   out of order.  LBM_EUNSUPPORTED: valid request the context does not
+ *   support (the adjoint with FP16/BF16 storage; the explicit-buffer step
+ *   calls with stochastic rounding).  LBM_EUNSTABLE: the
  *   diagnostics found a non-finite sum.
  * Field types.  The "compute real" R of a context is double for LBM_FP64
  *   and float for every other storage mode.  Arrays that carry the state in
@@ -189,7 +190,9 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 /* One step from lattice buffer src (state n) into dst (state n+1), outside
  * the ping-pong (used to recompute a segment of states for the adjoint).
  * src != dst; both lattice buffers of this context's layout.  Does not change
- * lbm_time or the current lattice. */
+ * lbm_time or the current lattice.  LBM_EUNSUPPORTED for a context with
+ * stochastic rounding: the call has no step index to key the random bits
+ * by (lbm_step has one). */
 lbm_status lbm_step_between(lbm_ctx* ctx, const void* src, void* dst);
 
 /* n >= 0 single steps that keep every state: states[0] = step(src),
@@ -199,7 +202,9 @@ lbm_status lbm_step_between(lbm_ctx* ctx, const void* src, void* dst);
  * reused once its state has been read (ping-pong).  The segment recompute
  * of a checkpointed adjoint.  Same result as n calls of lbm_step_between
  * (groups of four steps whose five buffers are distinct may run as one
- * fused launch).  Does not change lbm_time or the current lattice. */
+ * fused launch).  Does not change lbm_time or the current lattice.
+ * LBM_EUNSUPPORTED for a context with stochastic rounding (as
+ * lbm_step_between). */
 lbm_status lbm_step_sequence(lbm_ctx* ctx, const void* src, void* const* states, int64_t n);
 
 /* Copy the current lattice to dst (snapshot) / src to the current lattice

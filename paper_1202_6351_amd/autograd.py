@@ -82,7 +82,9 @@ class Rollout(torch.autograd.Function):
         ny, nx = params.ny, params.nx
         dev = force.device
         real = params.real_dtype
-        lat = Lattice(params, device=dev, force=force.detach())
+        # a copy: the backward works with the force field of the forward, even
+        # if the caller changes its tensor in place in between
+        lat = Lattice(params, device=dev, force=force.detach().to(device=dev, dtype=real, copy=True))
         f64 = torch.float64
         rho = (torch.full((ny, nx), params.rho0, dtype=f64, device=dev) if rho_init is None
                else rho_init.detach().to(dtype=f64).contiguous())

@@ -163,9 +163,6 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
     }
 }
 
-// Steps fused per launch: three for FP32 and FP64, whose two-step launch
-// leaves VALU idle while HBM streams; two for the 16-bit modes, whose
-// two-step launch already keeps VALU busy.
 // Steps fused per launch: four on the 64 x TY tiles in FP64 and FP32, two in
 // 16-bit storage.
 int steps_per_launch(int32_t storage) { return (storage == LBM_FP32 || storage == LBM_FP64) ? 4 : 2; }
@@ -332,15 +329,24 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   return LBM_OK;
 }
 
+// The explicit-buffer calls carry no step index, so they cannot draw fresh
+// stochastic-rounding bits per step: they refuse that rounding.
+static lbm_status no_stochastic(lbm_ctx* c, const char* what) {
+  set_err(c->err, "%s: stochastic rounding is supported by lbm_step only (no step index here)", what);
+  return LBM_EUNSUPPORTED;
+}
+
 lbm_status lbm_step_between(lbm_ctx* c, const void* src, void* dst) {
   if (!c) return LBM_EINVAL;
+  if (c->p.rounding == LBM_ROUND_STOCHASTIC) return no_stochastic(c, "step_between");
   if (!src || !dst || src == dst) return inval(c, "step_between: need distinct non-NULL src, dst");
   if (!aligned(src) || !aligned(dst)) return inval(c, "step_between: buffers must be 256-byte aligned");
-  return dev_err(c, lbm::launch_step(c->args, src, dst, step_key(c->p, c->t), c->stream), "step kernel");
+  return dev_err(c, lbm::launch_step(c->args, src, dst, 0u, c->stream), "step kernel");
 }
 
 lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, int64_t n) {
   if (!c) return LBM_EINVAL;
+  if (c->p.rounding == LBM_ROUND_STOCHASTIC) return no_stochastic(c, "step_sequence");
   if (n < 0) return inval(c, "step_sequence: n < 0");
   if (n > 0 && (!src || !states)) return inval(c, "step_sequence: need src and states");
   if (n > 0 && !aligned(src)) return inval(c, "step_sequence: buffers must be 256-byte aligned");
@@ -354,7 +360,7 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
   // as long as the group's five buffers are distinct, and a remainder of
   // three or two steps as one launch of that form cut short; the rest runs
   // as single steps.
-  const uint32_t key = step_key(c->p, c->t);
+  const uint32_t key = 0u;  // nearest rounding: the key is not used
   int64_t i = 0;
   const bool tiles4 = c->p.storage == LBM_FP32 && (int64_t)c->p.nx * c->p.ny <= lbm::kStep4MidMaxNodes;
   for (; tiles4 && i + 4 <= n; i += 4) {

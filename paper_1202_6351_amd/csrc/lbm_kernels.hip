@@ -821,8 +821,36 @@ __global__ __launch_bounds__(256) void k_macro(KArgs<typename Codec<S>::R> a, co
   }
 }
 
+// Sum of v over the 64 lanes of a wavefront: a butterfly over lane distances
+// 32, 16, ..., 1 (cross-lane permutes, no LDS, no barrier).  The order is
+// fixed, and both partners of each exchange add the same two values, so
+// every lane ends with the same, timing-independent sum.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Sums of acc[0..3] over a 256-thread block, in a fixed order: each
+// wavefront reduces its lanes, then thread k (< 4) adds the four wavefront
+// sums of quantity k.  Returns the block sum of quantity threadIdx.x in
+// threads 0..3.
+__device__ __forceinline__ double block_sum4(const double acc[4]) {
+  __shared__ double wsum[4][4];  // [wavefront][quantity]
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) wsum[wave][k] = s;
+  }
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x < 4) r = ((wsum[0][threadIdx.x] + wsum[1][threadIdx.x]) + wsum[2][threadIdx.x]) + wsum[3][threadIdx.x];
+  return r;
+}
+
 // Per-block FP64 partial sums of (rho - rho0, rho ux, rho uy, rho |u|^2 / 2).
-// Fixed grid and fixed reduction tree: the result does not depend on timing.
+// Fixed grid and fixed reduction order: the result does not depend on timing.
 template <typename S>
 __global__ __launch_bounds__(256) void k_diag_partial(KArgs<typename Codec<S>::R> a, const S* __restrict__ src,
                                                       double* __restrict__ partial) {
@@ -844,43 +872,18 @@ __global__ __launch_bounds__(256) void k_diag_partial(KArgs<typename Codec<S>::R
     acc[2] += rh * (double)vy;
     acc[3] += 0.5 * rh * ((double)vx * (double)vx + (double)vy * (double)vy);
   }
-  __shared__ double red[4][256];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 4) partial[(int64_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+  const double s = block_sum4(acc);
+  if (threadIdx.x < 4) partial[(int64_t)blockIdx.x * 4 + threadIdx.x] = s;
 }
 
 __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partial, int nblocks,
                                                     double base_mass, double* __restrict__ out) {
-  __shared__ double red[4][256];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = (int)threadIdx.x; b < nblocks; b += 256)
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] += partial[(int64_t)b * 4 + k];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[0] = base_mass + red[0][0];
-    out[1] = red[1][0];
-    out[2] = red[2][0];
-    out[3] = red[3][0];
-  }
+  const double s = block_sum4(acc);
+  if (threadIdx.x < 4) out[threadIdx.x] = threadIdx.x == 0 ? base_mass + s : s;
 }
 
 // Pull and its transpose for a node whose links all stay inside the domain

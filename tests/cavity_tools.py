@@ -190,47 +190,25 @@ def max_stable_cell_re_continuation(n, u_lid=0.1, start=40.0, factor=1.02, n_adv
     return rec
 
 
+def bounded_for_steps(n, u_lid, tau, steps):
+    """Alternate stability test (Sec. V): does the impulsively started n x n
+    cavity with lid speed u_lid and relaxation time tau stay bounded (speed
+    below 5 U, finite) for `steps` steps?"""
+    lat = cavity(n, u_lid, tau)
+    chunk = 1002
+    while lat.time < steps:
+        lat.step(min(chunk, steps - lat.time))
+        m = lat.macroscopic(strain=False)
+        umax = float((m["ux"] ** 2 + m["uy"] ** 2).sqrt().max())
+        if not np.isfinite(umax) or umax > 5 * u_lid:
+            return False
+    return True
+
+
 def max_stable_lid_speed(n=26, tau=0.55, steps=50_000, lo=1e-3, hi=1.0, rel=0.01):
-    """Alternate stability test (Sec. V): grid and viscosity fixed, the
-    largest lid speed at which the impulsively started n x n cavity stays
-    bounded (speed below 5 U, finite) for `steps` steps; geometric bisection
-    to a relative width rel."""
-    def ok(u_lid):
-        lat = cavity(n, u_lid, tau)
-        chunk = 1002
-        while lat.time < steps:
-            lat.step(min(chunk, steps - lat.time))
-            m = lat.macroscopic(strain=False)
-            umax = float((m["ux"] ** 2 + m["uy"] ** 2).sqrt().max())
-            if not np.isfinite(umax) or umax > 5 * u_lid:
-                return False
-        return True
+    """The largest lid speed for which bounded_for_steps holds; geometric
+    bisection to a relative width rel."""
     while hi / lo > 1 + rel:
         mid = (lo * hi) ** 0.5
-        lo, hi = (mid, hi) if ok(mid) else (lo, mid)
+        lo, hi = (mid, hi) if bounded_for_steps(n, mid, tau, steps) else (lo, mid)
     return lo
-
-
-if __name__ == "__main__":
-    # Prints the cavity convergence and stability figures of the GPU path:
-    #   python -m tests.cavity_tools convergence [ref_grid]
-    #   python -m tests.cavity_tools stability
-    #   python -m tests.cavity_tools lid-speed
-    import json
-    import sys
-    what = sys.argv[1] if len(sys.argv) > 1 else "convergence"
-    if what == "convergence":
-        ref = int(sys.argv[2]) if len(sys.argv) > 2 else 401
-        sl, er = convergence_slopes(ref=ref)
-        for k, v in sl.items():
-            print(json.dumps({"quantity": k[0], "line": k[1], "slope": round(v, 3), "ref": ref,
-                              "errors": [float(f"{e:.3e}") for e in er[k]]}), flush=True)
-    elif what == "lid-speed":
-        for tau in (0.505, 0.51, 0.52, 0.55, 0.6, 0.7, 0.8):
-            print(json.dumps({"n": 26, "tau": tau, "nu": round((tau - 0.5) / 3, 6), "steps": 50000,
-                              "max_stable_lid_speed": round(max_stable_lid_speed(tau=tau), 4)}), flush=True)
-    elif what == "stability":
-        for n in (101, 201, 401):
-            print(json.dumps({"n": n, "u_lid": 0.1,
-                              "impulsive": round(max_stable_cell_re(n), 2),
-                              "continuation": round(max_stable_cell_re_continuation(n), 2)}), flush=True)

@@ -82,3 +82,24 @@ def test_largest_plane_accepted():
     pitch, nbytes = lattice_layout(_params(nx=65536, ny=16383, storage="fp32"))
     assert pitch == 65536 and nbytes == 9 * 16383 * 65536 * 4
 
+
+
+def test_explicit_buffer_steps_refuse_stochastic_rounding():
+    """lbm_step_between and lbm_step_sequence take no step index, so they
+    could not draw fresh stochastic-rounding bits per step: with that
+    rounding they return LBM_EUNSUPPORTED before any device work (the
+    buffers below are never touched)."""
+    from paper_1202_6351_amd import _lib
+    lib = _lib.lib()
+    for storage in ("fp16", "bf16"):
+        cp = _params(storage=storage, rounding="stochastic").c()
+        ctx = ctypes.c_void_p()
+        a, b, c = (ctypes.c_void_p(0x100000 * k) for k in (1, 2, 3))
+        assert lib.lbm_create(ctypes.byref(cp), a, b, None, None, ctypes.byref(ctx)) == _lib.LBM_OK
+        try:
+            assert lib.lbm_step_between(ctx, a, c) == _lib.LBM_EUNSUPPORTED
+            assert b"stochastic" in lib.lbm_last_error(ctx)
+            arr = (ctypes.c_void_p * 2)(b.value, c.value)
+            assert lib.lbm_step_sequence(ctx, a, arr, 2) == _lib.LBM_EUNSUPPORTED
+        finally:
+            lib.lbm_destroy(ctx)

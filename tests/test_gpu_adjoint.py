@@ -5,7 +5,7 @@
 * the macroscopic and initial-state adjoints the same way;
 * full checkpointed rollouts: directional central differences on 32x32, and
   agreement with float64 torch autograd of the independent dense-matrix
-  formulation in oracle/ref_torch.py on 16x16.
+  formulation in oracle/ref_torch.py on 16x14 and 136x24 (FP64 and FP32).
 """
 import numpy as np
 import pytest
@@ -231,28 +231,51 @@ def test_rollout_finite_differences_32():
         assert abs(fd - an) <= 1e-5 * abs(an) + 1e-12 * gF.abs().max().item(), (i, fd, an)
 
 
+# (nx, ny, T, checkpoint interval, storage, tolerance relative to the largest
+# reference gradient entry).  16 x 14 has no tile away from the domain's
+# edges; on 136 x 24 the adjoint pairs (64 x 4 tiles) run their wall-free
+# form on the tiles at x0 = 64, y0 = 4 .. 16, and the forward its four-step
+# tiles (64 x 8).  FP32 bound: the FP32 forward and adjoint accumulate
+# rounding of order 1e-7 per step over T = 20 steps; measured errors are
+# about 1e-6 of the largest entry.
+AUTOGRAD_CASES = [
+    (16, 14, 30, 7, "fp64", 1e-10),
+    (136, 24, 20, 7, "fp64", 1e-10),
+    (136, 24, 20, 7, "fp32", 1e-4),
+]
+
+
+@pytest.mark.parametrize("case", range(len(AUTOGRAD_CASES)))
 @pytest.mark.parametrize("bci", range(len(BCS)))
-def test_rollout_matches_torch_autograd(bci):
-    """16x14 FP64 rollout, T = 30 (checkpoint every 7): gradients equal float64
-    torch autograd of the independent dense-matrix step."""
+def test_rollout_matches_torch_autograd(bci, case):
+    """Checkpointed rollouts (FP64, and the FP32 the benchmark runs): the
+    loss and the gradients with respect to the force field and the initial
+    velocity equal float64 torch autograd of the independent dense-matrix
+    step on the same (storage-rounded) inputs."""
     from paper_1202_6351_amd import Params, rollout
-    nx, ny, tau, T = 16, 14, 0.7, 30
+    nx, ny, T, every, storage, tol = AUTOGRAD_CASES[case]
+    tau = 0.7
     bc, wu = BCS[bci]
     kw = dict(tau=tau, omega3=1.1, omega6=0.9, omega7=1.2, omega8=1.3, bc=bc, wall_u=wu)
-    p = Params(nx, ny, storage="fp64", **kw)
+    p = Params(nx, ny, storage=storage, **kw)
+    real = p.real_dtype
     Fn = W.force_field(nx, ny, 1e-4, seed=7)
     rho_n, ux_n, uy_n = W.random_flow(nx, ny, seed=2, u_amp=0.03, rho_amp=0.0)
     tgt = np.stack(W.random_flow(nx, ny, seed=3, u_amp=0.03)[1:])
-    F = torch.from_numpy(Fn).to(DEV).requires_grad_(True)
-    u0 = torch.from_numpy(np.stack([ux_n, uy_n])).to(DEV).requires_grad_(True)
-    rho_T, u = rollout(p, F, u0, T, checkpoint_every=7)
-    target = torch.from_numpy(tgt).to(DEV)
+    F = torch.from_numpy(Fn).to(DEV, real).requires_grad_(True)
+    u0 = torch.from_numpy(np.stack([ux_n, uy_n])).to(DEV, real).requires_grad_(True)
+    rho_T, u = rollout(p, F, u0, T, checkpoint_every=every)
+    target = torch.from_numpy(tgt).to(DEV, real)
     L = ((u - target) ** 2).sum(dim=0).mean() + 0.3 * (rho_T ** 2).mean()
     L.backward()
 
-    # reference: torch autograd on the CPU
-    Ft = torch.from_numpy(Fn.reshape(2, -1).T.copy()).requires_grad_(True)
-    u0t = torch.from_numpy(np.stack([ux_n, uy_n]).reshape(2, -1)).requires_grad_(True)
+    # reference: torch autograd on the CPU, from the inputs as the GPU saw
+    # them (rounded to the compute real)
+    Fq = F.detach().double().cpu().numpy()
+    u0q = u0.detach().double().cpu().numpy()
+    tq = target.double().cpu().numpy()
+    Ft = torch.from_numpy(Fq.reshape(2, -1).T.copy()).requires_grad_(True)
+    u0t = torch.from_numpy(u0q.reshape(2, -1).copy()).requires_grad_(True)
     tab = ref_torch.stream_tables(nx, ny, [BCMAP[b] for b in bc], wu)
     om = p.c()
     omega = [0, 0, 0, om.omega3, om.omega_nu, om.omega_nu, om.omega6, om.omega7, om.omega8]
@@ -260,15 +283,17 @@ def test_rollout_matches_torch_autograd(bci):
     for _ in range(T):
         f = ref_torch.step(f, Ft, omega, tab)
     r, vx, vy = ref_torch.velocity(f, Ft)
-    tt = torch.from_numpy(tgt.reshape(2, -1))
+    tt = torch.from_numpy(tq.reshape(2, -1))
     Lr = ((vx - tt[0]) ** 2 + (vy - tt[1]) ** 2).mean() + 0.3 * (r ** 2).mean()
     Lr.backward()
-    assert abs(L.item() - Lr.item()) <= 1e-12 * abs(Lr.item())
+    assert abs(L.item() - Lr.item()) <= tol * abs(Lr.item())
     gF_ref = Ft.grad.T.reshape(2, ny, nx).numpy()
     gu_ref = u0t.grad.reshape(2, ny, nx).numpy()
-    gF, gu = F.grad.cpu().numpy(), u0.grad.cpu().numpy()
-    assert np.abs(gF - gF_ref).max() <= 1e-10 * np.abs(gF_ref).max()
-    assert np.abs(gu - gu_ref).max() <= 1e-10 * np.abs(gu_ref).max()
+    gF, gu = F.grad.double().cpu().numpy(), u0.grad.double().cpu().numpy()
+    eF = np.abs(gF - gF_ref).max() / np.abs(gF_ref).max()
+    eu = np.abs(gu - gu_ref).max() / np.abs(gu_ref).max()
+    print(f"{storage} {nx}x{ny} T={T}: grad F {eF:.2e}, grad u0 {eu:.2e} (max-norm, relative)")
+    assert eF <= tol and eu <= tol
 
 
 def test_rollout_fp32_gradient_close_to_fp64():
@@ -486,3 +511,24 @@ def test_step_sequence_large_shape(storage, bci, n):
         assert torch.equal(one, seq[i]), i
         prev = one
 
+
+
+def test_rollout_backward_uses_the_forward_force():
+    """The forward copies the force field: changing the caller's tensor in
+    place between forward and backward leaves the gradient unchanged."""
+    from paper_1202_6351_amd import Params, rollout
+    nx, ny, T = 40, 24, 9
+    p = Params(nx, ny, tau=0.7, storage="fp32")
+    F0 = torch.from_numpy(W.force_field(nx, ny, 1e-4, seed=9)).to(DEV, torch.float32)
+    u0 = torch.from_numpy(np.stack(W.random_flow(nx, ny, seed=5, u_amp=0.03)[1:])).to(DEV, torch.float32)
+    w = torch.from_numpy(np.random.default_rng(2).normal(size=(2, ny, nx))).to(DEV, torch.float32)
+    grads = []
+    for touch in (False, True):
+        F = F0.clone().requires_grad_(True)
+        _, u = rollout(p, F, u0, T, checkpoint_every=4)
+        if touch:
+            with torch.no_grad():
+                F.mul_(3.0).add_(1e-3)
+        (u * w).sum().backward()
+        grads.append(F.grad.clone())
+    assert torch.equal(grads[0], grads[1])
