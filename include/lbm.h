@@ -232,6 +232,24 @@ lbm_status lbm_macroscopic(lbm_ctx* ctx, void* rho, void* ux, void* uy,
  * Returns LBM_EUNSTABLE if any sum is not finite. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, double out[4]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
+ * lbm_diagnostics, with the same kernels and the same fixed reduction order
+ * (equal bit for bit), written to out, a device FP64 array of 4 (8-byte
+ * aligned) owned by the caller.  Asynchronous on the context's stream: no
+ * synchronisation, no copy to the host, no finiteness check (the caller reads
+ * out after the stream's work, and checks it).  The partial sums live in a
+ * static device array of the library, 1024 x 4 doubles (32 KiB) per GPU, held
+ * until the process ends; the call allocates nothing.  The need does not grow
+ * with the lattice (the reduction grid is fixed at 1024 blocks); a context
+ * whose grid exceeds the array is refused with LBM_EINVAL.  Every call on a
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.  The first
+ * call on a device looks up the array's device address (with that device
+ * current).  LBM_ESTATE before the state is set; LBM_EDEVICE on a HIP
+ * failure. */
+lbm_status lbm_diagnostics_noalloc(lbm_ctx* ctx, void* out);
+
 /* Adjoint (vector-Jacobian product) of one step n-1 -> n.  lat_prev: the
  * lattice buffer of state n-1 (as stored by the forward).  mu_in: cotangent
  * of the lattice buffer of state n, a device R array in lattice layout

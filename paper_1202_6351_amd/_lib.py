@@ -62,6 +62,7 @@ SIGNATURES = {
     "lbm_restore": (_st, [_vp, _vp, ctypes.c_int64]),
     "lbm_macroscopic": (_st, [_vp] * 7),
     "lbm_diagnostics": (_st, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "lbm_diagnostics_noalloc": (_st, [_vp, _vp]),
     "lbm_adjoint_step": (_st, [_vp] * 5),
     "lbm_adjoint_sequence": (_st, [_vp, ctypes.POINTER(_vp), ctypes.c_int64, _vp, _vp, _vp,
                                    ctypes.POINTER(ctypes.c_int)]),

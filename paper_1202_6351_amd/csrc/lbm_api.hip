@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "lbm.h"
@@ -191,6 +192,52 @@ lbm_status inval(lbm_ctx* c, const char* msg) {
 
 }  // namespace
 
+// Reduction scratch of lbm_diagnostics_noalloc: the per-block partial sums
+// (four doubles per block) of the fixed diagnostics grid.  A file-scope
+// device array, so the call never allocates; each GPU holds its own copy, at
+// its own address, until the process ends.
+constexpr int kDiagScratchBlocks = 1024;
+static __device__ __align__(256) double scratch[kDiagScratchBlocks * 4];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of the context's stream.  The
+// host-side name is only a stand-in for the symbol; its device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+lbm_status scratch_of(lbm_ctx* c, double** out) {
+  int dev = -1;
+  hipError_t e = c->stream ? hipStreamGetDevice(c->stream, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_err(c, e, "device of the context's stream");
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_err(c->err, "device %d beyond the %d devices the static scratch tracks", dev, kMaxDevices);
+    return LBM_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return dev_err(c, e, "current device");
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return dev_err(c, e, "select the stream's device");
+    void* p = nullptr;
+    const hipError_t es = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev && (e = hipSetDevice(cur)) != hipSuccess) return dev_err(c, e, "restore the current device");
+    if (es != hipSuccess) return dev_err(c, es, "address of the diagnostics scratch");
+    if (!p) {
+      set_err(c->err, "address of the diagnostics scratch: null");
+      return LBM_EDEVICE;
+    }
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 lbm_status lbm_lattice_layout(const lbm_params* p, int64_t* pitch, int64_t* bytes) {
@@ -230,7 +277,7 @@ lbm_status lbm_create(const lbm_params* p, void* lat0, void* lat1, const void* f
   else fill_args<float>(p, c->pitch, force_field, c->args.f);
   // Diagnostics: a fixed number of blocks (enough to fill 256 CUs), so the
   // reduction order does not depend on the grid size.
-  c->diag_blocks = 1024;
+  c->diag_blocks = kDiagScratchBlocks;
   c->diag_scratch = nullptr;  // allocated by the first lbm_diagnostics call
   c->err[0] = 0;
   *out = c;
@@ -453,6 +500,26 @@ lbm_status lbm_diagnostics(lbm_ctx* c, double out[4]) {
       return LBM_EUNSTABLE;
     }
   return LBM_OK;
+}
+
+lbm_status lbm_diagnostics_noalloc(lbm_ctx* c, void* out) {
+  if (!c) return LBM_EINVAL;
+  if (!out) return inval(c, "diagnostics_noalloc: out is NULL");
+  if (((uintptr_t)out & 7u) != 0) return inval(c, "diagnostics_noalloc: out must be 8-byte aligned");
+  if (!c->has_state) { set_err(c->err, "diagnostics before the state was set"); return LBM_ESTATE; }
+  if (c->diag_blocks > kDiagScratchBlocks) {
+    set_err(c->err, "diagnostics_noalloc: %d partial sums exceed the static scratch (%d)", c->diag_blocks,
+            kDiagScratchBlocks);
+    return LBM_EINVAL;
+  }
+  double* scr = nullptr;
+  lbm_status s = scratch_of(c, &scr);
+  if (s != LBM_OK) return s;
+  // Every partial sum is written before the final kernel reads it (same
+  // stream), so nothing in the scratch needs clearing.
+  const double base = (double)c->p.nx * (double)c->p.ny * c->p.rho0;
+  return dev_err(c, lbm::launch_diag(c->args, c->lat[c->cur], scr, c->diag_blocks, base, (double*)out, c->stream),
+                 "diagnostics kernel");
 }
 
 lbm_status lbm_adjoint_step(lbm_ctx* c, const void* lat_prev, const void* mu_in, void* mu_out, void* grad_force) {

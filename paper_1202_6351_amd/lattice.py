@@ -266,6 +266,17 @@ class Lattice:
         self._check(_lib.lib().lbm_diagnostics(self._ctx, out))
         return np.array(out[:], dtype=np.float64)
 
+    def diagnostics_noalloc(self, out: torch.Tensor) -> torch.Tensor:
+        """The same sums into `out` (device float64 [4]), asynchronously on
+        the library's stream, with the library's static scratch: no device
+        allocation, no synchronisation, no finiteness check."""
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= 4):
+            raise ValueError("out: need a contiguous device float64 tensor of 4 elements")
+        self._after_caller()
+        self._check(_lib.lib().lbm_diagnostics_noalloc(self._ctx, _ptr(out)))
+        self._before_caller()
+        return out
+
     # ------------------------------------------------------------- adjoint
     def adjoint_step(self, lat_prev, mu_in, mu_out, grad_force=None):
         self._after_caller()
