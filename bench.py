@@ -5,33 +5,42 @@
 Headline (`value`): MLUPS of the plain FP32 step on the lid-driven cavity
 4096 x 4096 (Re 1000, lid 0.1, tau 1.7288; seeded density noise 1e-6), with
 the lattices resident in HBM: W untimed steps, then exactly K steps (default
-100 000, the study's step count at its largest grid) timed with
-HIP events on the library's stream (lbm_step fuses four steps per launch in
-FP64 and FP32, two in FP16/BF16).  One JSON line on stdout, also carrying:
-  roofline      the dominant kernel (the four-step FP32 launch) against
-                MI355X's 8 TB/s: its algorithmic bytes per launch -- the
-                method's 72 B per FP32 cell update (nine populations read and
-                nine written) times the four updates of every node -- over
-                its measured average duration (an event between the whole
-                groups and any remainder of K separates the dominant
-                launches).  Fusing four steps moves only a quarter of those
-                bytes (the state read and written once per launch, 18 B per
-                update), so frac can exceed 1; the bytes actually moved and
-                their rate are reported beside it, and so is the VALU issue
-                rate from the committed SQ_INSTS_VALU count against the
-                chip's 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz;
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same cavity;
-  sizes         MLUPS of the same cavity at 1024^2 and 2048^2 (Re 1000) and
-                at 4096^2, Re 5000 (2100 steps each);
-  forms         FP16/BF16 deviation storage, round-to-nearest and
-                stochastic rounding, on Taylor-Green 8192 x 8192 (MLUPS;
-                algorithmic rate at 36 B per cell update and the rate of the
-                bytes moved, 36 B per node per two-step launch) with their
-                velocity and
-                strain-rate error against the FP64 path on Taylor-Green
-                512 x 512 after 20k steps at tau 0.8 and 0.55; forward + adjoint rollout MLUPS on
-                512 x 512 FP32 (T = 2000, checkpoint every 100) with the FP32
-                gradient's relative error against the FP64 gradient.
+100 000, the study's step count at its largest grid) timed with HIP events on
+the library's stream (lbm_step fuses four steps per launch in FP64 and FP32,
+two in FP16/BF16).  One JSON line on stdout, also carrying:
+
+  roofline      the dominant kernel, the four-step FP32 launch.  It keeps
+                the intermediate steps on chip and moves 18 B per update, so
+                it is bound by VALU issue, not by HBM: bound "alu", achieved =
+                the method's own operations per launch (97 VALU operations
+                per FP32 cell update at the default rates, times the four
+                updates of every node) over the launch's average duration
+                (HIP events between the whole groups and any remainder of K),
+                against 39.32 T VALU operations/s (256 CUs x 4 SIMDs x 16
+                lanes x 2.4 GHz; packed FP32 is not used).  Beside it: the
+                VALU issue fraction from the committed SQ_INSTS_VALU count,
+                flops against the FP32 vector peaks, and the HBM side: the
+                single-pass algorithmic rate at 72 B per update as a ratio of
+                8 TB/s (alg_hbm_ratio, above 1 by construction), the bytes the
+                launch actually moves and their fraction of 8 TB/s and of the
+                copy bandwidth measured in the same run;
+  copy          a plain device-to-device copy of 2 x 2 GiB timed in the run;
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline cavity;
+  cpu_plan      the oracle on the other configurations (all host threads and
+                one), the host's copy bandwidth, the CPU model, and the GPU /
+                oracle ratio per configuration;
+  sizes         the same cavity at 1024^2 and 2048^2 (Re 1000) and 4096^2
+                (Re 5000), FP32, each timed for at least 0.5 s, with the
+                FP32 velocity and strain-rate error against the FP64 path;
+  flows         FP32 Taylor-Green 8192^2 and Poiseuille channels (the
+                256 x 64 configuration and a 8192 x 2048 channel);
+  forms         FP16/BF16 deviation storage (nearest and stochastic
+                rounding) on Taylor-Green 8192^2 (MLUPS, roofline) with the
+                errors against the FP64 path on Taylor-Green 512^2 after 20k
+                steps at tau 0.8 and 0.55; the forward + adjoint rollout on
+                512 x 512 (T = 2000, checkpoint every 100) and 2048 x 2048
+                (T = 400) with the FP32 gradient's error against the FP64
+                gradient.
 """
 from __future__ import annotations
 
@@ -41,6 +50,7 @@ import json
 import math
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -48,37 +58,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-# Algorithmic bytes per cell update (nine populations read, nine written),
-# which is also what one node moves through HBM per launch: a launch reads
-# and writes the state once and advances every node by updates_per_launch
-# steps (the library's grouping).
-BYTES_PER_NODE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}
+# Algorithmic bytes per cell update: nine populations read, nine written.
+BYTES_PER_UPDATE = {"fp64": 144, "fp32": 72, "fp16": 36, "bf16": 36}
 METRIC = "MLUPS + % HBM peak, FP32 vs FP16-storage; fwd+adjoint MLUPS at fixed error"
 STEP_SOURCES = ["paper_1202_6351_amd/csrc/lbm_kernels.hip", "paper_1202_6351_amd/csrc/cascade.h",
                 "paper_1202_6351_amd/csrc/lbm_launch.h", "paper_1202_6351_amd/csrc/lbm_api.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step4_fp32_cavity4096.txt")
-VALU_FILE = os.path.join(ROOT, "profiles", "valu_step4_fp32_cavity4096.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed lane
-# instructions per second).
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# One FP32 collision without body force in the kernels' factorised form, at
-# the benchmark's omega_3 = omega_6 = omega_7 = omega_8 = 1 (the multiplies by
-# omega_6..8 are then left out): 97 VALU operations (31 add, 17 sub, 10 mul,
-# 38 fma, 1 rcp), 135 flops with an fma counted as two.  With other rates:
-# 100 operations, 138 flops.
-COLLISION_OPS_FP32, COLLISION_FLOPS_FP32 = 97, 135
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # published, packed FP32 FMA
+# operations per second; one wave64 instruction per SIMD every 4 cycles).
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+FP32_PEAK_TFLOPS_NONPACKED = 2 * VALU_PEAK_OPS / 1e12  # every lane an FMA: 78.6
+FP32_PEAK_TFLOPS_PUBLISHED = 157.3  # packed FP32 FMA
+# One FP32 cell update of the kernels' factorised collision, without body
+# force and at omega_3 = omega_6 = omega_7 = omega_8 = 1 (their multiplies
+# left out): 97 VALU operations (31 add, 17 sub, 10 mul, 38 fma, 1 rcp), 135
+# flops with an fma counted as two.  The 16-bit forms add one conversion per
+# population loaded and one per population stored (115).
+COLLISION_OPS = {"fp32": 97, "fp64": 97, "fp16": 115, "bf16": 115}
+COLLISION_FLOPS_FP32 = 135
 
 
-def updates_per_launch(storage: str, nodes: int) -> int:
-    """Steps the library fuses per launch: four on the 64 x TY tiles in FP64
-    and FP32, two in 16-bit storage."""
+def updates_per_launch(storage: str) -> int:
+    """Steps the library fuses per launch: four in FP64 and FP32, two in
+    16-bit storage."""
     return 2 if storage in ("fp16", "bf16") else 4
-
-
-def fp32_kernel(n: int) -> str:
-    """The kernel of an n x n FP32 lattice's fused launches."""
-    return "k_step4<float> (four steps per launch)"
 
 
 def kernel_hash() -> str:
@@ -89,9 +92,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _counter_value(path, key):
-    """A per-launch figure from a committed counter summary, if the counters
-    were taken on the current kernel source."""
+def counter_value(name, key):
+    """A per-launch figure from a committed counter summary under profiles/,
+    if the counters were taken on the current kernel sources (else None)."""
+    path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -100,16 +104,6 @@ def _counter_value(path, key):
     if not (m_hash and m_val) or m_hash.group(1) != kernel_hash():
         return None
     return float(m_val.group(1))
-
-
-def measured_traffic():
-    """HBM bytes per launch of the FP32 step (FETCH_SIZE + WRITE_SIZE)."""
-    return _counter_value(TRAFFIC_FILE, "traffic_bytes_per_launch")
-
-
-def measured_valu():
-    """VALU wave instructions per launch of the FP32 step (SQ_INSTS_VALU)."""
-    return _counter_value(VALU_FILE, "valu_wave_instructions_per_launch")
 
 
 def timed_steps(lat, steps, warmup, group):
@@ -132,6 +126,16 @@ def timed_steps(lat, steps, warmup, group):
     return e0.elapsed_time(e2) / 1e3, e0.elapsed_time(e1) / 1e3, whole // group
 
 
+def timed_for(lat, group, min_seconds=0.5):
+    """(MLUPS, seconds per launch) of whole-group launches, timed with HIP
+    events over at least min_seconds after a short calibration."""
+    nodes = lat.params.nx * lat.params.ny
+    _, dt, n = timed_steps(lat, 8 * group, 2 * group, group)
+    launches = max(8, int(math.ceil(min_seconds / max(dt / n, 1e-7))))
+    _, dt, n = timed_steps(lat, launches * group, 0, group)
+    return nodes * group * n / dt / 1e6, dt / n
+
+
 def cavity_lattice(n, storage, re=1000.0):
     import workloads as W
     from paper_1202_6351_amd import Lattice, Params
@@ -150,10 +154,60 @@ def taylor_green_lattice(n, storage, u0=0.05, tau=0.8, rounding="nearest"):
     return lat
 
 
-def cpu_baseline(n, tau, budget_s=15.0):
-    """The FP64 oracle on the same cavity, first steps from the same initial
-    state, on all host threads, for about budget_s of stepping (after one
-    untimed step that starts the thread pool)."""
+def poiseuille_lattice(nx, ny, storage, tau=0.8):
+    import workloads as W
+    from paper_1202_6351_amd import Lattice, Params
+    F = W.poiseuille_force(tau, 0.05, ny)
+    lat = Lattice(Params(nx, ny, tau=tau, fx=F, bc=("periodic", "periodic", "wall", "wall"), storage=storage),
+                  device="cuda:0")
+    lat.init_equilibrium(*W.at_rest(nx, ny))
+    return lat
+
+
+def field_errors(m, ref):
+    """Velocity (Sec. III norm) and strain-rate relative errors of m against
+    ref (numpy node fields)."""
+    import numpy as np
+    den_u = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).sum()
+    eu = np.sqrt((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2).sum() / den_u
+    s_num = sum(np.abs(m[k] - ref[k]).sum() for k in ("sxx", "syy", "sxy"))
+    s_den = sum(np.abs(ref[k]).sum() for k in ("sxx", "syy", "sxy"))
+    return float(f"{eu:.3e}"), float(f"{s_num / s_den:.3e}")
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Device-to-device copy of nbytes (read nbytes, write nbytes), timed with
+    HIP events: GB/s of bytes moved."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes * reps / dt / 1e9, 1)
+
+
+def alu_block(storage, nodes, per_launch):
+    """VALU roofline of a step launch from the method's operation count."""
+    grp = updates_per_launch(storage)
+    ops = COLLISION_OPS[storage]
+    achieved = ops * grp * nodes / per_launch / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_OPS / 1e12, 2),
+            "unit": "TOP/s", "frac": round(achieved * 1e12 / VALU_PEAK_OPS, 4), "ops_per_update": ops}
+
+
+def cpu_baseline(n, tau, budget_s=10.0):
+    """The FP64 oracle on the headline cavity, first steps from the same
+    initial state, on all host threads, for about budget_s of stepping (after
+    one untimed step that starts the thread pool)."""
     import oracle
     import workloads as W
     p = oracle.Params(n, n, tau=tau, bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
@@ -170,32 +224,147 @@ def cpu_baseline(n, tau, budget_s=15.0):
                       f"from the benchmark's initial state ({dt:.1f} s)"}
 
 
+# The oracle's share of the plan: (name, builder, steps on all threads, steps
+# on one thread).  Builders return (oracle params, initial state).
+def _plan_cases():
+    import oracle
+    import workloads as W
+
+    def tg64():
+        p = oracle.Params(64, 64, tau=0.8)
+        return p, oracle.init_state(p, *W.taylor_green(64, 0.01, noise=1e-5, seed=0))
+
+    def pois():
+        p = oracle.Params(256, 64, tau=0.8, fx=W.poiseuille_force(0.8, 0.05, 64), bc=(0, 0, 1, 1))
+        return p, oracle.init_state(p, *W.at_rest(256, 64))
+
+    def cav1024():
+        p = oracle.Params(1024, 1024, tau=W.cavity_tau(1024, 0.1, 1000.0), bc=(1, 1, 1, 1), wall_u=(0, 0, 0, 0.1))
+        return p, oracle.init_state(p, *W.at_rest(1024, 1024, density_noise=1e-6, seed=2))
+
+    def tg512():
+        p = oracle.Params(512, 512, tau=0.8)
+        return p, oracle.init_state(p, *W.taylor_green(512, 0.05, noise=1e-5, seed=0))
+
+    return [("taylor_green_64x64_fp64", tg64, 1000, 1000),
+            ("poiseuille_256x64_tau0.8", pois, 8000, 2000),
+            ("cavity_1024x1024_re1000", cav1024, 200, 12),
+            ("taylor_green_512x512", tg512, 200, 40)]
+
+
+def _oracle_plan_worker(single: bool):
+    """Runs in a child process (its own OpenMP thread count): oracle MLUPS
+    per plan configuration."""
+    import oracle
+    out = {}
+    for name, build, steps, steps1 in _plan_cases():
+        p, f = build()
+        n = steps1 if single else steps
+        f = oracle.step(p, f, 1)
+        t0 = time.perf_counter()
+        oracle.step(p, f, n)
+        dt = time.perf_counter() - t0
+        out[name] = {"steps": n, "seconds": round(dt, 3), "mlups": round(p.nx * p.ny * n / dt / 1e6, 2)}
+    out["threads"] = oracle.num_threads()
+    print(json.dumps(out))
+
+
+def host_copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Host memory copy bandwidth with torch's CPU threads (GB/s moved)."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    dt = time.perf_counter() - t0
+    return round(2 * nbytes * reps / dt / 1e9, 1), torch.get_num_threads()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def gpu_plan_rates():
+    """GPU MLUPS on the plan's configurations, FP64 (the oracle's arithmetic)
+    and the configuration's own storage, each timed for at least 0.5 s."""
+    import torch
+    out = {}
+    for name, mk, storages in (
+            ("taylor_green_64x64_fp64", lambda s: taylor_green_lattice(64, s, u0=0.01), ("fp64",)),
+            ("poiseuille_256x64_tau0.8", lambda s: poiseuille_lattice(256, 64, s), ("fp64", "fp32")),
+            ("cavity_1024x1024_re1000", lambda s: cavity_lattice(1024, s)[0], ("fp64", "fp32")),
+            ("taylor_green_512x512", lambda s: taylor_green_lattice(512, s), ("fp64", "fp32", "fp16", "bf16"))):
+        out[name] = {}
+        for st in storages:
+            lat = mk(st)
+            out[name][st] = round(timed_for(lat, updates_per_launch(st))[0], 1)
+            del lat
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_plan(gpu_rates):
+    """The oracle on the plan's configurations, on all host threads and on one,
+    in child processes; host copy bandwidth; GPU / oracle ratios."""
+    res = {}
+    for single in (False, True):
+        env = dict(os.environ)
+        if single:
+            env["OMP_NUM_THREADS"] = "1"
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-plan-worker",
+                            "single" if single else "all"], capture_output=True, text=True, env=env,
+                           timeout=300)
+        if r.returncode != 0:
+            raise RuntimeError(f"oracle plan worker failed: {r.stderr[-2000:]}")
+        res["one" if single else "all"] = json.loads(r.stdout.strip().splitlines()[-1])
+    bw, bw_threads = host_copy_bandwidth()
+    table = {}
+    for name in res["all"]:
+        if name == "threads":
+            continue
+        a, o = res["all"][name], res["one"][name]
+        g = gpu_rates.get(name, {})
+        table[name] = {"oracle_mlups": a["mlups"], "oracle_steps": a["steps"], "oracle_seconds": a["seconds"],
+                       "oracle_mlups_1core": o["mlups"],
+                       "oracle_frac_of_host_copy": round(a["mlups"] * 144 / 1e3 / bw, 4),
+                       "gpu_mlups": g,
+                       "gpu_fp64_over_oracle": (round(g["fp64"] / a["mlups"], 1) if "fp64" in g else None)}
+    return {"kind": "oracle", "threads": res["all"]["threads"], "cpu_model": cpu_model(),
+            "host_copy_gbs": bw, "host_copy_threads": bw_threads,
+            "oracle_bytes_per_update": 144, "configs": table}
+
+
 def precision_errors(n=512, steps=20000, tau=0.8):
-    """Velocity and strain-rate relative error (Sec. III norm) of FP32, FP16
-    and BF16 storage against the FP64 path, Taylor-Green n x n, U0 0.05,
-    noise 1e-5, relaxation time tau."""
-    import numpy as np
+    """Velocity and strain-rate relative error of FP32, FP16 and BF16 storage
+    against the FP64 path, Taylor-Green n x n, U0 0.05, noise 1e-5."""
     import torch
     out = {}
     ref = taylor_green_lattice(n, "fp64", tau=tau).step(steps).macroscopic()
     ref = {k: v.cpu().numpy() for k, v in ref.items()}
-    den_u = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).sum()
     for storage, rounding in (("fp32", "nearest"), ("fp16", "nearest"), ("bf16", "nearest"),
                               ("fp16", "stochastic"), ("bf16", "stochastic")):
         m = taylor_green_lattice(n, storage, tau=tau, rounding=rounding).step(steps).macroscopic()
         m = {k: v.cpu().numpy() for k, v in m.items()}
-        eu = np.sqrt((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2).sum() / den_u
-        es = np.abs(m["sxx"] - ref["sxx"]).sum() / np.abs(ref["sxx"]).sum()
+        eu, es = field_errors(m, ref)
         key = storage if rounding == "nearest" else f"{storage}_sr"
-        out[key] = {"u_rel_err": float(f"{eu:.3e}"), "sxx_rel_err": float(f"{es:.3e}")}
+        out[key] = {"u_rel_err": eu, "strain_rel_err": es}
     torch.cuda.synchronize()
     return {"workload": f"taylor_green_{n}x{n}_u0.05_tau{tau}_{steps}steps", "reference": "fp64 GPU path",
             **out}
 
 
 def adjoint_rollout(n=512, T=2000, every=100):
-    """Forward + adjoint of the differentiable rollout (512 x 512 periodic,
-    force field N(0, 1e-6^2) seed 4, u0 = 0, Taylor-Green target U0 = 0.02)."""
+    """Forward + adjoint of the differentiable rollout (n x n periodic, force
+    field N(0, 1e-6^2) seed 4, u0 = 0, Taylor-Green target U0 = 0.02), FP32
+    timed (second pass), with the FP32 gradient against the FP64 one."""
     import numpy as np
     import torch
     import workloads as W
@@ -213,7 +382,7 @@ def adjoint_rollout(n=512, T=2000, every=100):
         p = Params(n, n, tau=0.8, storage=storage)
         # the first pass pays the device allocations of snapshots and the
         # segment buffer; the second one (same sizes, cached) is timed
-        for _ in range(2):
+        for _ in range(2 if storage == "fp32" else 1):
             F = torch.from_numpy(W.force_field(n, n, 1e-6, seed=4)).to("cuda", real).requires_grad_(True)
             u0 = torch.zeros(2, n, n, dtype=real, device="cuda", requires_grad=True)
             torch.cuda.synchronize()
@@ -224,6 +393,8 @@ def adjoint_rollout(n=512, T=2000, every=100):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
         res[storage] = (dt, F.grad.double().cpu().numpy(), u0.grad.double().cpu().numpy())
+        del F, u0, u, loss
+        torch.cuda.empty_cache()
     dt = res["fp32"][0]
     errF = np.abs(res["fp32"][1] - res["fp64"][1]).sum() / np.abs(res["fp64"][1]).sum()
     erru = np.abs(res["fp32"][2] - res["fp64"][2]).sum() / np.abs(res["fp64"][2]).sum()
@@ -243,20 +414,33 @@ def copy_calibration(nbytes=1 << 30):
     torch.cuda.synchronize()
 
 
+def cavity_errors(n, re, steps):
+    """FP32 against the FP64 path on the cavity after `steps` steps (the
+    FP64 path equals the oracle to 1e-12 in the parity tests)."""
+    m32 = {k: v.cpu().numpy() for k, v in cavity_lattice(n, "fp32", re)[0].step(steps).macroscopic().items()}
+    m64 = {k: v.cpu().numpy() for k, v in cavity_lattice(n, "fp64", re)[0].step(steps).macroscopic().items()}
+    eu, es = field_errors(m32, m64)
+    return {"steps": steps, "u_rel_err": eu, "strain_rel_err": es, "reference": "fp64 GPU path"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
-    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout"], default=None,
+    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout", "rollout2048"], default=None,
                     help="time one storage mode, or the forward + adjoint rollout, only (profiling runs)")
     ap.add_argument("--rounding", choices=["nearest", "stochastic"], default="nearest",
                     help="16-bit rounding of an --only fp16/bf16 run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--oracle-plan-worker", choices=["all", "single"], default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_plan_worker:
+        _oracle_plan_worker(args.oracle_plan_worker == "single")
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU domain decomposition is a design note only).", file=sys.stderr)
@@ -268,16 +452,19 @@ def main():
     if args.only == "rollout":
         print(json.dumps({"only": "rollout", **adjoint_rollout()}))
         return
+    if args.only == "rollout2048":
+        print(json.dumps({"only": "rollout2048", **adjoint_rollout(2048, 400, 100)}))
+        return
 
     if args.only in ("fp16", "bf16", "fp64"):
         n = 8192 if args.only != "fp64" else 4096
         rounding = args.rounding if args.only != "fp64" else "nearest"
         lat = (taylor_green_lattice(n, args.only, rounding=rounding) if args.only != "fp64"
                else cavity_lattice(n, "fp64")[0])
-        grp = updates_per_launch(args.only, n * n)
+        grp = updates_per_launch(args.only)
         dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
         mlups = n * n * args.steps / dt / 1e6
-        gbs = BYTES_PER_NODE[args.only] * n * n * launches / dt_main / 1e9 if launches else None
+        gbs = BYTES_PER_UPDATE[args.only] * n * n * launches / dt_main / 1e9 if launches else None
         print(json.dumps({"only": args.only, "rounding": rounding, "n": n, "mlups": round(mlups, 1),
                           "updates_per_launch": grp, "moved_gbs": None if gbs is None else round(gbs, 1),
                           "launch_us": round(dt_main / launches * 1e6, 2) if launches else None}))
@@ -285,17 +472,45 @@ def main():
 
     n = args.n
     lat, tau = cavity_lattice(n, "fp32")
-    grp = updates_per_launch("fp32", n * n)
+    grp = updates_per_launch("fp32")
     if args.steps < grp:
         raise SystemExit(f"--steps must be at least {grp} (one fused launch)")
     dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
     mlups = n * n * args.steps / dt / 1e6
     per_launch = dt_main / launches
-    moved = BYTES_PER_NODE["fp32"] * n * n / per_launch / 1e9  # HBM bytes the launch moves
-    achieved = moved * grp  # algorithmic: 72 B per cell update, grp updates per node
+    nodes = n * n
+    moved = BYTES_PER_UPDATE["fp32"] * nodes / per_launch / 1e9  # the state read and written once per launch
+    alg = moved * grp  # single pass: 72 B per cell update
     d = lat.diagnostics()  # raises on a non-finite state
-    traffic = measured_traffic() if n == 4096 else None
-    valu = measured_valu() if n == 4096 else None
+    headline = n == 4096
+    traffic = counter_value("traffic_step4_fp32_cavity4096.txt", "traffic_bytes_per_launch") if headline else None
+    valu = counter_value("valu_step4_fp32_cavity4096.txt", "valu_wave_instructions_per_launch") if headline else None
+    del lat
+    torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth()
+    roof = alu_block("fp32", nodes, per_launch)
+    roof.update({
+        "traffic": None if traffic is None else round(traffic),
+        "kernel": "k_step4<float> (four steps per launch)", "launch_us": round(per_launch * 1e6, 2),
+        "updates_per_launch": grp,
+        "valu_issue": None if valu is None else {
+            "lane_instructions_per_update": round(valu * 64 / (grp * nodes), 1),
+            "achieved_tops": round(valu * 64 / per_launch / 1e12, 2),
+            "frac": round(valu * 64 / per_launch / VALU_PEAK_OPS, 4)},
+        "flops": {"per_update": COLLISION_FLOPS_FP32,
+                  "achieved_tflops": round(COLLISION_FLOPS_FP32 * grp * nodes / per_launch / 1e12, 2),
+                  "peak_tflops_nonpacked": round(FP32_PEAK_TFLOPS_NONPACKED, 1),
+                  "peak_tflops_published_packed": FP32_PEAK_TFLOPS_PUBLISHED},
+        "hbm": {"alg_bytes_per_update": BYTES_PER_UPDATE["fp32"], "alg_gbs": round(alg, 1),
+                "alg_hbm_ratio": round(alg / HBM_PEAK_GBS, 4),
+                "moved_bytes_per_update": BYTES_PER_UPDATE["fp32"] / grp, "moved_gbs": round(moved, 1),
+                "moved_frac": round(moved / HBM_PEAK_GBS, 4), "copy_gbs": copy_gbs,
+                "moved_vs_copy": round(moved / copy_gbs, 4)},
+        "note": f"{grp} steps per launch keep the intermediate states on chip: the launch moves "
+                f"{BYTES_PER_UPDATE['fp32'] / grp:g} B per update and is bound by VALU issue.  frac is the "
+                "method's own operations against the VALU issue peak; valu_issue.frac counts every issued "
+                "instruction (recompute rings, staging, addressing included); alg_hbm_ratio is the "
+                "single-pass 72 B/update rate over 8 TB/s, which temporal blocking lets exceed 1."})
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
@@ -303,70 +518,62 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cavity_{n}x{n}_re1000_fp32", "nx": n, "ny": n, "tau": round(tau, 6),
                    "lid_u": 0.1, "storage": "fp32", "bc": "halfway bounce-back walls, moving lid"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic),
-                     "kernel": fp32_kernel(n),
-                     "launch_us": round(per_launch * 1e6, 2),
-                     "updates_per_launch": grp,
-                     "alg_bytes_per_update": BYTES_PER_NODE["fp32"],
-                     "moved_bytes_per_update": BYTES_PER_NODE["fp32"] / grp,
-                     "moved_gbs": round(moved, 1), "moved_frac": round(moved / HBM_PEAK_GBS, 4),
-                     "valu": None if valu is None else {
-                         "lane_instructions_per_update": round(valu * 64 / (grp * n * n), 1),
-                         "achieved_tops": round(valu * 64 / per_launch / 1e12, 2),
-                         "peak_tops": round(VALU_PEAK_LANE_OPS / 1e12, 2),
-                         "frac": round(valu * 64 / per_launch / VALU_PEAK_LANE_OPS, 4)},
-                     "collision": {
-                         "ops_per_update": COLLISION_OPS_FP32, "flops_per_update": COLLISION_FLOPS_FP32,
-                         "ops_frac": round(COLLISION_OPS_FP32 * grp * n * n / per_launch / VALU_PEAK_LANE_OPS, 4),
-                         "achieved_tflops": round(COLLISION_FLOPS_FP32 * grp * n * n / per_launch / 1e12, 2),
-                         "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_TFLOPS},
-                     "note": f"{grp} steps per launch: the state crosses HBM once per {grp} updates, "
-                             "so the algorithmic rate exceeds the single-pass HBM roofline.  The launch "
-                             "is bound by VALU issue (valu.frac of 256 CUs x 64 lanes x 2.4 GHz; the "
-                             "collision's own operations are collision.ops_frac of it, the rest is the "
-                             "recompute ring and staging); its moved bytes run at moved_frac of HBM "
-                             "peak (a plain copy reaches 5.07 TB/s)"},
-        "mass_drift_rel": float(f"{abs(d[0] / (n * n) - 1.0):.2e}"),
+        "roofline": roof,
+        "copy": {"gbs": copy_gbs, "what": "device-to-device copy, 2 GiB read + 2 GiB written, HIP events"},
+        "mass_drift_rel": float(f"{abs(d[0] / nodes - 1.0):.2e}"),
     }
-    del lat
-    torch.cuda.empty_cache()
     if args.only is None and not args.no_forms:
-        # the other grids and Reynolds number of the same cavity throughput study
+        # the other grids and Reynolds number of the cavity throughput study
         sizes = {}
         for ns, re in ((1024, 1000.0), (2048, 1000.0), (4096, 5000.0)):
             ls, _ = cavity_lattice(ns, "fp32", re)
-            dts, _, _ = timed_steps(ls, 2100, 300, updates_per_launch("fp32", ns * ns))
-            sizes[f"cavity_{ns}x{ns}_re{int(re)}_fp32"] = round(ns * ns * 2100 / dts / 1e6, 1)
+            m, pl = timed_for(ls, grp)
+            sizes[f"cavity_{ns}x{ns}_re{int(re)}_fp32"] = {
+                "mlups": round(m, 1), "launch_us": round(pl * 1e6, 2), "roofline": alu_block("fp32", ns * ns, pl),
+                "error_vs_fp64": cavity_errors(ns, re, 2000)}
             del ls
             torch.cuda.empty_cache()
+        sizes[f"cavity_{n}x{n}_re1000_fp32"] = {"error_vs_fp64": cavity_errors(n, 1000.0, 2000)}
         line["sizes"] = sizes
-    if args.only is None and not args.no_forms:
+        flows = {}
+        for key, mk in (("taylor_green_8192x8192_fp32", lambda: taylor_green_lattice(8192, "fp32")),
+                        ("poiseuille_256x64_fp32", lambda: poiseuille_lattice(256, 64, "fp32")),
+                        ("poiseuille_256x64_fp64", lambda: poiseuille_lattice(256, 64, "fp64")),
+                        ("poiseuille_8192x2048_fp32", lambda: poiseuille_lattice(8192, 2048, "fp32"))):
+            lf = mk()
+            st = lf.params.storage
+            m, pl = timed_for(lf, updates_per_launch(st))
+            flows[key] = {"mlups": round(m, 1), "launch_us": round(pl * 1e6, 2),
+                          "roofline": alu_block(st, lf.params.nx * lf.params.ny, pl),
+                          "alg_hbm_ratio": round(m * BYTES_PER_UPDATE[st] / 1e3 / HBM_PEAK_GBS, 4)}
+            del lf
+            torch.cuda.empty_cache()
+        line["flows"] = flows
         forms = {}
         for storage in ("fp16", "bf16"):
             for rounding in ("nearest", "stochastic"):
                 l16 = taylor_green_lattice(8192, storage, rounding=rounding)
-                g16 = updates_per_launch(storage, 8192 * 8192)
-                steps16 = max(10, min(args.steps // 4, 2000))
-                steps16 -= steps16 % g16
-                dt16, _, launches16 = timed_steps(l16, steps16, max(2, args.warmup // 4), g16)
-                m16 = 8192 * 8192 * steps16 / dt16 / 1e6
-                moved16 = BYTES_PER_NODE[storage] * 8192 * 8192 / (dt16 / launches16) / 1e9
-                alg16 = BYTES_PER_NODE[storage] * m16 / 1e3  # 36 B per cell update
+                g16 = updates_per_launch(storage)
+                m16, pl16 = timed_for(l16, g16)
+                moved16 = BYTES_PER_UPDATE[storage] * 8192 * 8192 / pl16 / 1e9
+                alg16 = BYTES_PER_UPDATE[storage] * m16 / 1e3
                 key = f"{storage}_dev" if rounding == "nearest" else f"{storage}_dev_sr"
                 forms[key] = {"workload": "taylor_green_8192x8192", "rounding": rounding,
-                              "mlups": round(m16, 1), "updates_per_launch": g16,
-                              "alg_gbs": round(alg16, 1), "alg_frac": round(alg16 / HBM_PEAK_GBS, 4),
-                              "moved_gbs": round(moved16, 1), "moved_frac": round(moved16 / HBM_PEAK_GBS, 4)}
+                              "mlups": round(m16, 1), "updates_per_launch": g16, "launch_us": round(pl16 * 1e6, 2),
+                              "roofline": alu_block(storage, 8192 * 8192, pl16),
+                              "alg_gbs": round(alg16, 1), "alg_hbm_ratio": round(alg16 / HBM_PEAK_GBS, 4),
+                              "moved_gbs": round(moved16, 1), "moved_frac": round(moved16 / HBM_PEAK_GBS, 4),
+                              "moved_vs_copy": round(moved16 / copy_gbs, 4)}
                 del l16
                 torch.cuda.empty_cache()
         forms["error_vs_fp64"] = precision_errors()
         forms["error_vs_fp64_tau0.55"] = precision_errors(tau=0.55)
         forms["fwd_adjoint"] = adjoint_rollout()
+        forms["fwd_adjoint_2048"] = adjoint_rollout(2048, 400, 100)
         line["forms"] = forms
     if args.only is None and not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, tau)
+        line["cpu_plan"] = cpu_plan(gpu_plan_rates())
     print(json.dumps(line))
 
 
