@@ -623,6 +623,154 @@ __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& 
   }
 }
 
+// ---- interior tiles ------------------------------------------------------
+//
+// A tile whose window and the window's own pulls stay inside the domain (no
+// wall link, no wrap), on a lattice below 4 GiB.  A stage's region is a
+// rectangle of RW x RH window cells, numbered row-major; cell i lies at
+// window index i + (i / RW) (EW - RW) + c0.  Every HBM address of the stage
+// is the window origin's plus that cell's element offset (one scalar base,
+// one per-cell offset), every LDS access a per-cell index plus a
+// compile-time offset, and no cell takes a wall or wrap decision.
+
+// Force of a window cell: none, the uniform one, or the field's.
+template <int FM, typename R>
+__device__ __forceinline__ void core_force(const KArgs<R>& a, int gx, int gy, R& Fx, R& Fy) {
+  Fx = R(0);
+  Fy = R(0);
+  if constexpr (FM == 1) {
+    Fx = a.fx;
+    Fy = a.fy;
+  } else if constexpr (FM == 2) {
+    node_force(a, gx, gy, Fx, Fy);
+  }
+}
+
+// First stage: step n on every window cell, from HBM into LDS.  A thread's
+// cells go in batches of B: the loads of a whole batch are issued before its
+// first collision.
+template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U, int B>
+__device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>& a,
+                                               const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
+                                               int wx0, int wy0, uint32_t key, S (&mid)[9][EH][EW]) {
+  using R = typename Codec<S>::R;
+  constexpr int NC = EW * EH, NPT = (NC + NT - 1) / NT;
+  const Geom& g = a.g;
+  const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
+  const uint32_t base = (uint32_t)(wy0 * g.pitch + wx0);  // element index of window cell 0
+  const uint32_t skip = (uint32_t)(g.pitch - EW);
+  S* lds = &mid[0][0][0];
+  const int t = (int)threadIdx.x;
+#pragma unroll
+  for (int j0 = 0; j0 < NPT; j0 += B) {
+    R d[B][9];
+#pragma unroll
+    for (int jb = 0; jb < B; ++jb) {
+      const int j = j0 + jb, i = t + NT * j;
+      if (j < NPT && (NC % NT == 0 || j + 1 < NPT || i < NC)) {
+        const uint32_t cy = (uint32_t)i / (uint32_t)EW;
+        const uint32_t off = (base + (uint32_t)i + cy * skip) * (uint32_t)sizeof(S);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) d[jb][k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
+      }
+    }
+#pragma unroll
+    for (int jb = 0; jb < B; ++jb) {
+      const int j = j0 + jb, i = t + NT * j;
+      if (j < NPT && (NC % NT == 0 || j + 1 < NPT || i < NC)) {
+        const int cy = i / EW, gx = wx0 + (i - cy * EW), gy = wy0 + cy;
+        R Fx, Fy;
+        core_force<FM>(a, gx, gy, Fx, Fy);
+        R out[9];
+        collide_step<R, FM != 0, U>(rt, Fx, Fy, d[jb], out);
+        S o[9];
+        round_out<S, SR>(out, SR ? (uint32_t)(gy * g.nx + gx) : 0u, key, o);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) lds[k * NC + i] = o[k];
+      }
+    }
+  }
+}
+
+// Middle stage, in place: one step on the window cells at most RING nodes
+// outside the tile (the window has an H-node ring).  Every thread pulls and
+// collides its cells into registers; after a barrier it writes them back.
+template <typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U>
+__device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>& a,
+                                               const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
+                                               uint32_t key, S (&mid)[9][EH][EW]) {
+  using R = typename Codec<S>::R;
+  constexpr int M = H - RING, RW = EW - 2 * M, RH = EH - 2 * M, NC = RW * RH, NPT = (NC + NT - 1) / NT;
+  constexpr int PL = EH * EW;
+  S* lds = &mid[0][0][0];
+  const int t = (int)threadIdx.x;
+  S o[NPT][9];
+  int w[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = t + NT * j;
+    w[j] = 0;
+    if (NC % NT == 0 || j + 1 < NPT || i < NC) {
+      const int ry = (int)((uint32_t)i / (uint32_t)RW);
+      w[j] = i + ry * (EW - RW) + M * (EW + 1);
+      R d[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(lds[k * PL + w[j] - EY[k] * EW - EX[k]]);
+      const int gx = wx0 + M + (i - ry * RW), gy = wy0 + M + ry;
+      R Fx, Fy;
+      core_force<FM>(a, gx, gy, Fx, Fy);
+      R out[9];
+      collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
+      round_out<S, SR>(out, SR ? (uint32_t)(gy * a.g.nx + gx) : 0u, key, o[j]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = t + NT * j;
+    if (NC % NT == 0 || j + 1 < NPT || i < NC) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) lds[k * PL + w[j]] = o[j][k];
+    }
+  }
+  __syncthreads();
+}
+
+// Last stage: one step on the 64 x TY tile from LDS to HBM.
+template <typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U>
+__device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>& a,
+                                               const Rates<typename Codec<S>::R>& rt, int x0, int y0,
+                                               uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst) {
+  using R = typename Codec<S>::R;
+  constexpr int PL = EH * EW;
+  const Geom& g = a.g;
+  const S* lds = &mid[0][0][0];
+  const __amdgpu_buffer_rsrc_t wr = rsrc(dst, g.lattice_bytes);
+  const int lx = (int)threadIdx.x & 63;
+  const uint32_t obase = (uint32_t)(y0 * g.pitch + x0 + lx);
+#pragma unroll
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += NT / 64) {
+    const int w = (ly + H) * EW + lx + H;
+    R d[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(lds[k * PL + w - EY[k] * EW - EX[k]]);
+    R Fx, Fy;
+    core_force<FM>(a, x0 + lx, y0 + ly, Fx, Fy);
+    R out[9];
+    collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
+    S o[9];
+    round_out<S, SR>(out, SR ? (uint32_t)((y0 + ly) * g.nx + x0 + lx) : 0u, key, o);
+    const uint32_t off = (obase + (uint32_t)ly * (uint32_t)g.pitch) * (uint32_t)sizeof(S);
+    if (g.wb_stores) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(wr, off, g.st_soff[k], o[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) BufIO<S>::store(wr, off, g.st_soff[k], o[k]);
+    }
+  }
+}
+
 // Tile origin of this workgroup; interior: every pull of the window with an
 // H-node ring stays inside the domain (no wall link, no wrap); fast: interior
 // and the lattice takes the buffer path.
@@ -650,6 +798,14 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t2_tiles_x, x0, y0, interior, fast);
+  if constexpr (FM != 2) {
+    if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
+      core_stage_hbm<S, FM, SR, EH, EW, 256, U, 2>(a, rt, src, x0 - H, y0 - H, key_a, mid);
+      __syncthreads();
+      core_stage_out<S, FM, SR, TY, EH, EW, H, 256, U>(a, rt, x0, y0, key_b, mid, dst);
+      return;
+    }
+  }
   stage_from_hbm<S, FM, SR, EH, EW, U>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
   if (interior)  // workgroup-uniform
@@ -675,6 +831,15 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
+  if constexpr (FM != 2) {
+    if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
+      core_stage_hbm<S, FM, SR, EH, EW, NT, false, 3>(a, rt, src, x0 - H, y0 - H, key_a, mid);
+      __syncthreads();
+      core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, false>(a, rt, x0 - H, y0 - H, key_b, mid);
+      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, false>(a, rt, x0, y0, key_c, mid, dst);
+      return;
+    }
+  }
   stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
   if (interior) {  // workgroup-uniform: every thread meets the same barriers
@@ -718,6 +883,16 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
+  if constexpr (!KEEP && FM != 2) {
+    if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
+      core_stage_hbm<S, FM, SR, EH, EW, NT, U, 3>(a, rt, src, x0 - H, y0 - H, key_a, mid);
+      __syncthreads();
+      core_stage_lds<S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
+      core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
+      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U>(a, rt, x0, y0, key_d, mid, dst);
+      return;
+    }
+  }
   stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, U, FW, KEEP>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid, fw,
                                                                keep0);
   __syncthreads();
