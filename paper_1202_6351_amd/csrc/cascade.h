@@ -78,16 +78,6 @@ LBM_HD Rates<R> make_rates(const R w[6], R rho0) {
 LBM_HD float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 LBM_HD double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Intermediates of the forward pass that the reverse pass needs.
-template <typename R>
-struct NodeFwd {
-  R M[3][3];   // raw moments of d, M[m][n] ~ e_x^m e_y^n
-  R X[3][3];   // after the x shift to central
-  R D[3][3];   // change of the central moments in the collision
-  R Y[3][3];   // after the y shift of D back to raw
-  R ux, uy, inv_rho, drho;
-};
-
 // ------------------------------------------------------ 3-point operators
 // Moments of (p-, p0, p+) on {-1, 0, +1}: m0 = sum, m1 = p+ - p-, m2 = p+ + p-.
 template <typename R>
@@ -185,64 +175,6 @@ LBM_HD void equilibrium_cm_T(R r0, R ux, R uy, const R aCs[3][3], R& adrho,
   auy = fmad(r0, fmad(uy, gy, fmad(-ux, aCs[1][1], fmad(R(1.0 / 3.0) + ux2, aCs[2][1], aCs[0][1]))), auy);
 }
 
-// Collision increment of the central moments, Delta C = C* - C:
-//   Delta C_00 = 0, Delta C_10 = F_x, Delta C_01 = F_y (-F/2 -> +F/2),
-//   Delta(C_20 + C_02) = w3 (E_s - (C_20 + C_02)),
-//   Delta(C_20 - C_02) = w4 (E_d - (C_20 - C_02)),
-//   Delta C_11 = w5 (E_11 - C_11), Delta C_21 = w6 (E_21 - C_21),
-//   Delta C_12 = w7 (E_12 - C_12), Delta C_22 = w8 (E_22 - C_22),
-// E being the equilibrium central moments (deviation form).
-template <typename R>
-LBM_HD void relax_delta(const Rates<R>& r, R drho, R ux, R uy, R Fx, R Fy,
-                                            const R C[3][3], R D[3][3]) {
-  R E[3][3];
-  equilibrium_cm(r.rho0, drho, ux, uy, R(0), R(0), E);
-  D[0][0] = R(0);
-  D[1][0] = Fx;
-  D[0][1] = Fy;
-  const R ds = r.w3 * ((E[2][0] + E[0][2]) - (C[2][0] + C[0][2]));
-  const R dd = r.w4 * ((E[2][0] - E[0][2]) - (C[2][0] - C[0][2]));
-  D[2][0] = R(0.5) * (ds + dd);
-  D[0][2] = R(0.5) * (ds - dd);
-  D[1][1] = r.w5 * (E[1][1] - C[1][1]);
-  D[2][1] = r.w6 * (E[2][1] - C[2][1]);
-  D[1][2] = r.w7 * (E[1][2] - C[1][2]);
-  D[2][2] = r.w8 * (E[2][2] - C[2][2]);
-}
-
-// Reverse of relax_delta: cotangent aD -> aC (C_00, C_10, C_01 get none) and
-// accumulations into adrho, aux, auy, aFx, aFy.
-template <typename R>
-LBM_HD void relax_delta_T(const Rates<R>& r, R ux, R uy, const R aD[3][3],
-                                              R aC[3][3], R& adrho, R& aux, R& auy, R& aFx,
-                                              R& aFy) {
-  aFx += aD[1][0];
-  aFy += aD[0][1];
-  const R as = r.hw3 * (aD[2][0] + aD[0][2]);  // cotangent of the s target
-  const R ad = r.hw4 * (aD[2][0] - aD[0][2]);  // cotangent of the d target
-  R aE[3][3];
-  aE[0][0] = R(0);
-  aE[1][0] = R(0);
-  aE[0][1] = R(0);
-  aE[2][0] = as + ad;
-  aE[0][2] = as - ad;
-  aE[1][1] = r.w5 * aD[1][1];
-  aE[2][1] = r.w6 * aD[2][1];
-  aE[1][2] = r.w7 * aD[1][2];
-  aE[2][2] = r.w8 * aD[2][2];
-  aC[0][0] = R(0);
-  aC[1][0] = R(0);
-  aC[0][1] = R(0);
-  aC[2][0] = -aE[2][0];
-  aC[0][2] = -aE[0][2];
-  aC[1][1] = -aE[1][1];
-  aC[2][1] = -aE[2][1];
-  aC[1][2] = -aE[1][2];
-  aC[2][2] = -aE[2][2];
-  R unused_x = R(0), unused_y = R(0);
-  equilibrium_cm_T(r.rho0, ux, uy, aE, adrho, aux, auy, unused_x, unused_y);
-}
-
 // ------------------------------------------------------------ node passes
 // Raw moments of a node's d (x then y).
 template <typename R>
@@ -323,70 +255,146 @@ LBM_HD void node_fields(const Rates<R>& r, const R M[3][3], R Fx, R Fy,
   uy = (M[0][1] + R(0.5) * Fy) * inv_rho;
 }
 
-// One collision: d (pre-collision deviations) -> out (post-collision), with
-// the intermediates in s.  out = d + T^-1 Sh(+u) Delta C (see header).
+// Transposed Jacobian of the collision at the pre-collision deviations d:
+// given the cotangent a of the post-collision deviations, returns the
+// cotangent ad of d and adds the force cotangent to aFx, aFy.  The forward
+// part recomputes only what the reverse part reads (raw and central moments,
+// u, the increments Delta C and their back-shifted values, no post-collision
+// populations); the reverse part takes each step of the collision backwards
+// (inverse transform, back shift, relaxation with its attractors, shift to
+// central moments, hydrodynamic fields, raw moments) and leaves out the terms
+// of the structural zeros: Delta C_00 = 0, Delta C_10 = F_x and Delta C_01 =
+// F_y (their cotangents go to the force only), and C_00, C_10, C_01 are not
+// relaxed (no cotangent reaches them).
 template <typename R>
-LBM_HD void collide(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9],
-                                        NodeFwd<R>& s) {
-  raw_moments(d, s.M);
-  // the fields of node_fields, with 1/rho as in the step kernels' collision
-  s.drho = s.M[0][0];
-  s.inv_rho = recip(r.rho0 + s.drho);
-  s.ux = (s.M[1][0] + R(0.5) * Fx) * s.inv_rho;
-  s.uy = (s.M[0][1] + R(0.5) * Fy) * s.inv_rho;
-  R C[3][3];
-  central(s.ux, s.uy, s.M, s.X, C);
-  relax_delta(r, s.drho, s.ux, s.uy, Fx, Fy, C, s.D);
-  R inc[9];
-  populations(s.ux, s.uy, s.D, s.Y, inc);
+LBM_HD void collide_adj(const Rates<R>& r, R Fx, R Fy, const R d[9], const R a[9], R ad[9], R& aFx, R& aFy) {
+  const R r0 = r.rho0, third = R(1.0 / 3.0);
+  // ---------------------------------------------------------------- forward
+  R M[3][3];
+  raw_moments(d, M);
+  const R drho = M[0][0];
+  const R inv = recip(r0 + drho);
+  const R ux = fmad(R(0.5), Fx, M[1][0]) * inv;
+  const R uy = fmad(R(0.5), Fy, M[0][1]) * inv;
+  R X1[3], X2[3];  // after the x shift: X[1][n], X[2][n] (X[0][n] = M[0][n])
 #pragma unroll
-  for (int k = 0; k < 9; ++k) out[k] = d[k] + inc[k];
-}
-
-// Transposed Jacobian of collide() at the state recorded in s: given the
-// cotangent aout of the output, returns the cotangent ad of d and adds the
-// force cotangent to aFx, aFy.
-template <typename R>
-LBM_HD void collide_T(const Rates<R>& r, const NodeFwd<R>& s, const R aout[9],
-                                          R ad[9], R& aFx, R& aFy) {
-  R aux = R(0), auy = R(0), adrho = R(0);
-  R aD[3][3];
-  populations_T(s.ux, s.uy, s.D, s.Y, aout, aD, aux, auy);
-  R aC[3][3];
-  relax_delta_T(r, s.ux, s.uy, aD, aC, adrho, aux, auy, aFx, aFy);
-  R aX[3][3];
+  for (int n = 0; n < 3; ++n) {
+    X1[n] = fmad(-ux, M[0][n], M[1][n]);
+    X2[n] = fmad(-ux, M[1][n] + X1[n], M[2][n]);
+  }
+  const R C01 = fmad(-uy, M[0][0], M[0][1]);
+  const R C02 = fmad(-uy, M[0][1] + C01, M[0][2]);
+  const R C11 = fmad(-uy, X1[0], X1[1]);
+  const R C12 = fmad(-uy, X1[1] + C11, X1[2]);
+  const R C20 = X2[0];
+  const R C21 = fmad(-uy, X2[0], X2[1]);
+  const R C22 = fmad(-uy, X2[1] + C21, X2[2]);
+  const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+  const R tx = third + ux2, ty = third + uy2;
+  // increments Delta C = omega (E - C) of the relaxed moments (E: the
+  // attractors in deviation form)
+  const R ds = r.w3 * (fmad(-r0, ux2 + uy2, R(2.0 / 3.0) * drho) - (C20 + C02));
+  const R dd = r.w4 * (-r0 * (ux2 - uy2) - (C20 - C02));
+  const R D20 = R(0.5) * (ds + dd), D02 = R(0.5) * (ds - dd);
+  const R D11 = r.w5 * fmad(-r0, uxy, -C11);
+  const R D21 = r.w6 * fmad(r0 * uy, tx, -C21);
+  const R D12 = r.w7 * fmad(r0 * ux, ty, -C12);
+  // back shift by +u (y, then x): the values whose cotangents carry u
+  const R uy2x = uy + uy, ux2x = ux + ux;
+  const R Y02 = fmad(uy2x, Fy, D02);
+  const R Y11 = fmad(uy, Fx, D11);
+  const R Y12 = fmad(uy, D11 + Y11, D12);
+  const R Y21 = fmad(uy, D20, D21);
+  const R Mo11 = fmad(ux, Fy, Y11);
+  const R Mo12 = fmad(ux, Y02, Y12);
+  // ---------------------------------------------------------------- reverse
+  // inverse transform (x rows, then y), transposed
+  R aB[3][3], aMo[3][3];
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
-    ax_ctr_T(s.uy, s.X[m][0], s.X[m][1], aC[m][0], aC[m][1], aC[m][2], aX[m][0], aX[m][1], aX[m][2], auy);
+  for (int J = 0; J < 3; ++J) ax_inv_T(a[DIR[J][0]], a[DIR[J][1]], a[DIR[J][2]], aB[J][0], aB[J][1], aB[J][2]);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) ax_inv_T(aB[0][m], aB[1][m], aB[2][m], aMo[m][0], aMo[m][1], aMo[m][2]);
+  // x shift by +ux, transposed; the shifted column n = 0 is (0, F_x, .),
+  // n = 1 is (F_y, Mo11, .), n = 2 is (Y02, Mo12, .)
+  R aY[3][3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    aY[2][n] = aMo[2][n];
+    aY[1][n] = fmad(ux2x, aMo[2][n], aMo[1][n]);
+    aY[0][n] = fmad(ux, fmad(ux, aMo[2][n], aMo[1][n]), aMo[0][n]);
+  }
+  R aux = R(2) * (Fx * aMo[2][0]);
+  aux = fmad(Fy, aMo[1][1], fmad(Mo11 + Mo11, aMo[2][1], aux));
+  aux = fmad(Y02, aMo[1][2], fmad(Mo12 + Mo12, aMo[2][2], aux));
+  // y shift by +uy, transposed, per row m (Delta C_m0, Delta C_m1, Delta C_m2)
+  const R aD02 = aY[0][2], aD01 = fmad(uy2x, aY[0][2], aY[0][1]);
+  const R aD12 = aY[1][2], aD11 = fmad(uy2x, aY[1][2], aY[1][1]);
+  const R aD10 = fmad(uy, fmad(uy, aY[1][2], aY[1][1]), aY[1][0]);
+  const R aD22 = aY[2][2], aD21 = fmad(uy2x, aY[2][2], aY[2][1]);
+  const R aD20 = fmad(uy, fmad(uy, aY[2][2], aY[2][1]), aY[2][0]);
+  R auy = R(2) * (Fy * aY[0][2]);
+  auy = fmad(Fx, aY[1][1], fmad(Y11 + Y11, aY[1][2], auy));
+  auy = fmad(D20, aY[2][1], fmad(Y21 + Y21, aY[2][2], auy));
+  aFx += aD10;
+  aFy += aD01;
+  // relaxation, transposed: the cotangents of E - C per relaxed moment
+  const R as = r.hw3 * (aD20 + aD02), adv = r.hw4 * (aD20 - aD02);
+  const R a11 = r.w5 * aD11, a21 = r.w6 * aD21, a12 = r.w7 * aD12, a22 = r.w8 * aD22;
+  const R aC20 = -(as + adv), aC02 = adv - as;
+  R adrho = fmad(R(2.0 / 3.0), as, R(1.0 / 9.0) * a22);
+  // attractors: d/d(u_x^2), d/d(u_y^2), d/d(u_x u_y), then the chain to u
+  const R aux2 = fmad(-r0, fmad(ty, a22, as + adv), r0 * uy * a21);
+  const R auy2 = fmad(-r0, fmad(tx, a22, as - adv), r0 * ux * a12);
+  const R auxy = -r0 * a11;
+  aux = fmad(ux2x, aux2, fmad(uy, auxy, fmad(r0 * ty, a12, aux)));
+  auy = fmad(uy2x, auy2, fmad(ux, auxy, fmad(r0 * tx, a21, auy)));
+  // y shift to central moments, transposed (aC_00 = aC_10 = aC_01 = 0; the
+  // cotangents of C_11, C_21, C_12, C_22 are -a11, -a21, -a12, -a22)
+  const R aX02 = aC02, aX01 = -uy2x * aC02, aX00 = uy * uy * aC02;
+  const R aX12 = -a12, aX11 = fmad(uy2x, a12, -a11);
+  const R aX10 = -uy * fmad(uy, a12, -a11);
+  const R aX22 = -a22, aX21 = fmad(uy2x, a22, -a21);
+  const R aX20 = fmad(-uy, fmad(uy, a22, -a21), aC20);
+  auy = fmad(R(-2) * C01, aC02, auy);
+  auy = fmad(X1[0], a11, fmad(C11 + C11, a12, auy));
+  auy = fmad(X2[0], a21, fmad(C21 + C21, a22, auy));
+  // x shift to central moments, transposed, per column n
+  const R aXc[3][3] = {{aX00, aX01, aX02}, {aX10, aX11, aX12}, {aX20, aX21, aX22}};
   R aM[3][3];
 #pragma unroll
-  for (int n = 0; n < 3; ++n)
-    ax_ctr_T(s.ux, s.M[0][n], s.M[1][n], aX[0][n], aX[1][n], aX[2][n], aM[0][n], aM[1][n], aM[2][n], aux);
-  // u = j / rho with j = (M_10 + F_x/2, M_01 + F_y/2), rho = rho0 + M_00.
-  const R ajx = aux * s.inv_rho, ajy = auy * s.inv_rho;
-  aM[0][0] += adrho - (aux * s.ux + auy * s.uy) * s.inv_rho;
+  for (int n = 0; n < 3; ++n) {
+    aM[2][n] = aXc[2][n];
+    aM[1][n] = fmad(-ux2x, aXc[2][n], aXc[1][n]);
+    aM[0][n] = fmad(-ux, fmad(-ux, aXc[2][n], aXc[1][n]), aXc[0][n]);
+    aux = fmad(-M[0][n], aXc[1][n], fmad(R(-2) * X1[n], aXc[2][n], aux));
+  }
+  // u = (M_10 + F_x/2, M_01 + F_y/2) / (rho0 + M_00)
+  const R ajx = aux * inv, ajy = auy * inv;
+  aM[0][0] += adrho - fmad(ajx, ux, ajy * uy);
   aM[1][0] += ajx;
   aM[0][1] += ajy;
-  aFx += R(0.5) * ajx;
-  aFy += R(0.5) * ajy;
+  aFx = fmad(R(0.5), ajx, aFx);
+  aFy = fmad(R(0.5), ajy, aFy);
+  // raw moments, transposed; the identity path adds a
   R aA[3][3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) ax_mom_T(aM[m][0], aM[m][1], aM[m][2], aA[0][m], aA[1][m], aA[2][m]);
-  // out = d + increment: the identity path adds aout to the cotangent of d.
 #pragma unroll
   for (int J = 0; J < 3; ++J) {
     R a0, a1, a2;
     ax_mom_T(aA[J][0], aA[J][1], aA[J][2], a0, a1, a2);
-    ad[DIR[J][0]] = aout[DIR[J][0]] + a0;
-    ad[DIR[J][1]] = aout[DIR[J][1]] + a1;
-    ad[DIR[J][2]] = aout[DIR[J][2]] + a2;
+    ad[DIR[J][0]] = a[DIR[J][0]] + a0;
+    ad[DIR[J][1]] = a[DIR[J][1]] + a1;
+    ad[DIR[J][2]] = a[DIR[J][2]] + a2;
   }
 }
 
-// The collision of the step kernels: the same function as collide(), in the
-// fewest operations.  Differences from collide()'s route, all exact in real
-// arithmetic: Delta C_00 = 0 and, without a body force, Delta C_10 =
-// Delta C_01 = 0, so those terms are dropped; without a body force the
+// The collision of the step kernels, in the fewest operations: raw moments,
+// the fields, central moments (shift in x, then y), the increments Delta C =
+// omega (E - C) of the relaxed moments, back shift and inverse transform
+// added to d.  Simplifications, all exact in real arithmetic: Delta C_00 =
+// 0 and, without a body force, Delta C_10 = Delta C_01 = 0, so those terms
+// are dropped; without a body force the
 // first-order central moments of d are rho0 u, which stand in for the
 // products rho0 u_x, rho0 u_y of the attractors; the 2 Delta C_11, and
 // twice the outer rows of the y inverse, are carried so that the factors 1/2

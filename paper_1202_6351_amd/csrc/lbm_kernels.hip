@@ -1094,16 +1094,12 @@ __global__ __launch_bounds__(256) void k_adjoint_step(KArgs<typename Codec<S>::R
   else gather<S, R>(a.g, a.wadd, prev, p.x, p.y, d);
   R Fx, Fy;
   node_force(a, p.x, p.y, Fx, Fy);
-  const Rates<R> r = rates(a);
-  R out[9];
-  NodeFwd<R> s;
-  collide(r, Fx, Fy, d, out, s);
   const int64_t c = (int64_t)p.y * a.g.pitch + p.x;
   R mu[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * a.g.plane + c];
   R nu[9], aFx = R(0), aFy = R(0);
-  collide_T(r, s, mu, nu, aFx, aFy);
+  collide_adj(rates(a), Fx, Fy, d, mu, nu, aFx, aFy);
   // Reverse streaming: the transpose of the gather permutation.
   if (inner) scatter_inner<R>(a.g, mu_out, p.x, p.y, nu);
   else scatter<R, R>(a.g, a.wadd, mu_out, p.x, p.y, nu, false);
@@ -1142,14 +1138,11 @@ __device__ __forceinline__ void adjoint_pair_tile(const KArgs<typename Codec<S>:
     else gather_inner<S, R>(g, prev_a, gx, gy, d);
     R Fx, Fy;
     node_force(a, gx, gy, Fx, Fy);
-    R out[9];
-    NodeFwd<R> st;
-    collide(r, Fx, Fy, d, out, st);
     const int64_t c = (int64_t)gy * g.pitch + gx;
     R mu[9], nu[9], ax = R(0), ay = R(0);
 #pragma unroll
     for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * g.plane + c];
-    collide_T(r, st, mu, nu, ax, ay);
+    collide_adj(r, Fx, Fy, d, mu, nu, ax, ay);
     if constexpr (WALLS) {
       const Edges e = edges(g, gx, gy);
 #define LBM_SCATTER_WIN(A)                                                        \
@@ -1183,13 +1176,10 @@ __device__ __forceinline__ void adjoint_pair_tile(const KArgs<typename Codec<S>:
     else gather_inner<S, R>(g, prev_b, gx, gy, d);
     R Fx, Fy;
     node_force(a, gx, gy, Fx, Fy);
-    R out[9];
-    NodeFwd<R> st;
-    collide(r, Fx, Fy, d, out, st);
     R mu[9], nu[9], ax = R(0), ay = R(0);
 #pragma unroll
     for (int k = 0; k < 9; ++k) mu[k] = mid[k][ly + H][lx + H];
-    collide_T(r, st, mu, nu, ax, ay);
+    collide_adj(r, Fx, Fy, d, mu, nu, ax, ay);
     if constexpr (WALLS) scatter<R, R>(g, a.wadd, mu_out, gx, gy, nu, false);
     else scatter_inner<R>(g, mu_out, gx, gy, nu);
     if (grad_force) {

@@ -11,28 +11,19 @@ lbm::Rates<double> rates_of(const double* w, double rho0) {
 
 extern "C" {
 
-// General collision (used by the adjoint's forward pass).  d, out: deviations.
-void host_collide(const double* d, double Fx, double Fy, const double* w, double rho0, double* out) {
-  lbm::NodeFwd<double> s;
-  lbm::collide(rates_of(w, rho0), Fx, Fy, d, out, s);
-}
-
-// The step kernel's specialised collision (force = 0: no body force).
+// The step kernels' collision (force = 0: no body force).
 void host_collide_step(const double* d, double Fx, double Fy, const double* w, double rho0, int force,
                        double* out) {
   if (force) lbm::collide_step<double, true>(rates_of(w, rho0), Fx, Fy, d, out);
   else lbm::collide_step<double, false>(rates_of(w, rho0), 0.0, 0.0, d, out);
 }
 
-// Transposed Jacobian of the collision at d: ad = J_d^T aout, aF = J_F^T aout.
-void host_collide_T(const double* d, double Fx, double Fy, const double* w, double rho0, const double* aout,
-                    double* ad, double* aF) {
-  lbm::NodeFwd<double> s;
-  double out[9];
-  const lbm::Rates<double> r = rates_of(w, rho0);
-  lbm::collide(r, Fx, Fy, d, out, s);
+// Transposed Jacobian of the collision at d (the adjoint kernels' collide_adj):
+// ad = J_d^T aout, aF = J_F^T aout.
+void host_collide_adj(const double* d, double Fx, double Fy, const double* w, double rho0, const double* aout,
+                      double* ad, double* aF) {
   double ax = 0.0, ay = 0.0;
-  lbm::collide_T(r, s, aout, ad, ax, ay);
+  lbm::collide_adj(rates_of(w, rho0), Fx, Fy, d, aout, ad, ax, ay);
   aF[0] = ax;
   aF[1] = ay;
 }
