@@ -40,7 +40,8 @@ two in FP16/BF16).  One JSON line on stdout, also carrying:
                 steps at tau 0.8 and 0.55; the forward + adjoint rollout on
                 512 x 512 (T = 2000, checkpoint every 100) and 2048 x 2048
                 (T = 400) with the FP32 gradient's error against the FP64
-                gradient.
+                gradient; the adjoint pair launch at 2048^2 on its own, with
+                its HBM roofline (168 B per node and launch).
 """
 from __future__ import annotations
 
@@ -403,6 +404,48 @@ def adjoint_rollout(n=512, T=2000, every=100):
             "grad_u0_rel_err_vs_fp64": float(f"{erru:.3e}")}
 
 
+def adjoint_pair_roofline(n=2048, pairs=50, copy_gbs=None):
+    """The adjoint pair launch (k_adjoint_step2, two adjoint steps) on an
+    n x n periodic FP32 lattice with a force field, timed with HIP events over
+    `pairs` launches: its HBM roofline at the algorithmic 168 B per node and
+    launch (two states 72, cotangent in 36 and out 36, force 8, force gradient
+    read and written 16)."""
+    import torch
+    import workloads as W
+    from paper_1202_6351_amd import Lattice, Params
+    lat = Lattice(Params(n, n, tau=0.8, storage="fp32"), device="cuda:0",
+                  force=torch.from_numpy(W.force_field(n, n, 1e-6, seed=4)))
+    lat.init_equilibrium(*W.taylor_green(n, 0.02))
+    states = [lat.new_lattice() for _ in range(3)]
+    lat.step_sequence(lat.snapshot(), states)
+    mu_a, mu_b = lat.new_cotangent(), lat.new_cotangent()
+    mu_a.normal_()
+    gF = torch.zeros((2, n, n), dtype=torch.float32, device="cuda")
+    seq = [states[0], states[1]]
+    lat.adjoint_sequence(seq, mu_a, mu_b, gF)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    for _ in range(pairs):
+        lat.adjoint_sequence(seq, mu_a, mu_b, gF)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) / 1e3 / pairs
+    alg = 168 * n * n / per / 1e9
+    traffic = counter_value("traffic_adjoint2_fp32_2048.txt", "traffic_bytes_per_launch") if n == 2048 else None
+    valu = counter_value("valu_adjoint2_fp32_2048.txt", "valu_wave_instructions_per_launch") if n == 2048 else None
+    out = {"kernel": "k_adjoint_step2<float> (two adjoint steps per launch)", "workload": f"adjoint_{n}x{n}_fp32",
+           "launch_us": round(per * 1e6, 2), "adjoint_glups": round(2 * n * n / per / 1e9, 2),
+           "roofline": {"bound": "hbm", "achieved": round(alg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
+                        "alg_bytes_per_node": 168,
+                        "vs_copy": None if not copy_gbs else round(alg / copy_gbs, 4)}}
+    if valu is not None:
+        out["valu_issue"] = {"lane_instructions_per_node_step": round(valu * 64 / (2 * n * n), 1),
+                             "frac": round(valu * 64 / per / VALU_PEAK_OPS, 4)}
+    return out
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain elementwise copy kernel of known size (reads and writes nbytes),
     so that counter runs can scale the step kernel's FETCH_SIZE / WRITE_SIZE
@@ -558,9 +601,17 @@ def main():
                 moved16 = BYTES_PER_UPDATE[storage] * 8192 * 8192 / pl16 / 1e9
                 alg16 = BYTES_PER_UPDATE[storage] * m16 / 1e3
                 key = f"{storage}_dev" if rounding == "nearest" else f"{storage}_dev_sr"
+                roof16 = alu_block(storage, 8192 * 8192, pl16)
+                if storage == "fp16" and rounding == "nearest":
+                    v16 = counter_value("valu_step2_fp16_taylor_green8192.txt", "valu_wave_instructions_per_launch")
+                    t16 = counter_value("traffic_step2_fp16_taylor_green8192.txt", "traffic_bytes_per_launch")
+                    roof16["traffic"] = None if t16 is None else round(t16)
+                    roof16["valu_issue"] = None if v16 is None else {
+                        "lane_instructions_per_update": round(v16 * 64 / (g16 * 8192 * 8192), 1),
+                        "frac": round(v16 * 64 / pl16 / VALU_PEAK_OPS, 4)}
                 forms[key] = {"workload": "taylor_green_8192x8192", "rounding": rounding,
                               "mlups": round(m16, 1), "updates_per_launch": g16, "launch_us": round(pl16 * 1e6, 2),
-                              "roofline": alu_block(storage, 8192 * 8192, pl16),
+                              "roofline": roof16,
                               "alg_gbs": round(alg16, 1), "alg_hbm_ratio": round(alg16 / HBM_PEAK_GBS, 4),
                               "moved_gbs": round(moved16, 1), "moved_frac": round(moved16 / HBM_PEAK_GBS, 4),
                               "moved_vs_copy": round(moved16 / copy_gbs, 4)}
@@ -570,6 +621,7 @@ def main():
         forms["error_vs_fp64_tau0.55"] = precision_errors(tau=0.55)
         forms["fwd_adjoint"] = adjoint_rollout()
         forms["fwd_adjoint_2048"] = adjoint_rollout(2048, 400, 100)
+        forms["adjoint_pair_2048"] = adjoint_pair_roofline(2048, copy_gbs=copy_gbs)
         line["forms"] = forms
     if args.only is None and not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, tau)

@@ -402,14 +402,13 @@ lbm_status lbm_step_sequence(lbm_ctx* c, const void* src, void* const* states, i
     if (!states[i] || states[i] == prev) return inval(c, "step_sequence: states[i] NULL or equal to its input");
     if (!aligned(states[i])) return inval(c, "step_sequence: buffers must be 256-byte aligned");
   }
-  // FP32 lattices of up to kStep4MidMaxNodes nodes run groups of four steps
-  // as one four-step launch that also stores the three intermediate states,
-  // as long as the group's five buffers are distinct, and a remainder of
-  // three or two steps as one launch of that form cut short; the rest runs
-  // as single steps.
+  // FP32 lattices run groups of four steps as one four-step launch that also
+  // stores the three intermediate states, as long as the group's five
+  // buffers are distinct, and a remainder of three or two steps as one launch
+  // of that form cut short; the rest runs as single steps.
   const uint32_t key = 0u;  // nearest rounding: the key is not used
   int64_t i = 0;
-  const bool tiles4 = c->p.storage == LBM_FP32 && (int64_t)c->p.nx * c->p.ny <= lbm::kStep4MidMaxNodes;
+  const bool tiles4 = c->p.storage == LBM_FP32;
   for (; tiles4 && i + 4 <= n; i += 4) {
     const void* in = i == 0 ? src : states[i - 1];
     void *k0 = states[i], *k1 = states[i + 1], *k2 = states[i + 2], *out = states[i + 3];

@@ -1474,7 +1474,8 @@ hipError_t launch_step4_keep(const KArgsAny& a, const void* src, void* keep0, vo
   if (a.f.g.t4_ty == kStep4TyF32Mid)
     return launch_step4_fm<float, kStep4TyF32Mid, kStep4ThreadsF32Mid, true>(a.f, src, dst, keep0, keep1, keep2,
                                                                              key_a, key_b, key_c, key_d, st);
-  return hipErrorInvalidValue;  // the 64 x 24 tiles (lattices above kStep4MidMaxNodes) take no kept states
+  return launch_step4_fm<float, kStep4TyF32, kStep4ThreadsF32, true>(a.f, src, dst, keep0, keep1, keep2, key_a, key_b,
+                                                                     key_c, key_d, st);
 }
 
 hipError_t launch_step(const KArgsAny& a, const void* src, void* dst, uint32_t key, hipStream_t st) {

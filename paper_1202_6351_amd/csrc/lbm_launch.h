@@ -116,8 +116,7 @@ hipError_t launch_step4(const KArgsAny& a, const void* src, void* dst, uint32_t 
 // keep1, keep2 (src, keep0..2, dst pairwise distinct): the same result as
 // four launch_step calls src -> keep0 -> keep1 -> keep2 -> dst.  dst null:
 // three steps, up to keep2; keep2 and dst null: two steps, up to keep1.
-// FP32 on lattices of up to kStep4MidMaxNodes nodes only (else
-// hipErrorInvalidValue).
+// FP32 only (else hipErrorInvalidValue).
 hipError_t launch_step4_keep(const KArgsAny& a, const void* src, void* keep0, void* keep1, void* keep2, void* dst,
                              uint32_t key_a, uint32_t key_b, uint32_t key_c, uint32_t key_d, hipStream_t st);
 hipError_t launch_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy, void* dst,
