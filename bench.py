@@ -24,7 +24,8 @@ two in FP16/BF16).  One JSON line on stdout, also carrying:
                 8 TB/s (alg_hbm_ratio, above 1 by construction), the bytes the
                 launch actually moves and their fraction of 8 TB/s and of the
                 copy bandwidth measured in the same run;
-  copy          a plain device-to-device copy of 2 x 2 GiB timed in the run;
+  copy          a plain device-to-device copy of 2 x 2 GiB timed in the run
+                (first, before the headline's lattice is made);
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline cavity;
   cpu_plan      the oracle on the other configurations (all host threads and
                 one), the host's copy bandwidth, the CPU model, and the GPU /
@@ -446,6 +447,49 @@ def adjoint_pair_roofline(n=2048, pairs=50, copy_gbs=None):
     return out
 
 
+def single_step_rates(n=8192, copy_gbs=None, min_seconds=0.5):
+    """One step per launch (lbm_step_between, the single-step kernel) on the
+    Taylor-Green n^2 lattice in FP32, FP16 and BF16: the launch reads and
+    writes the state once, so HBM bounds it and the 16-bit storage halves
+    its bytes."""
+    import torch
+    out = {}
+    for storage in ("fp32", "fp16", "bf16"):
+        lat = taylor_green_lattice(n, storage)
+        a, b = lat.lat[0], lat.lat[1]
+        if lat.current is not a:
+            a, b = b, a
+        s = lat.stream
+        for _ in range(4):
+            lat.step_between(a, b)
+            lat.step_between(b, a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(4):
+            lat.step_between(a, b)
+            lat.step_between(b, a)
+        e1.record(s)
+        torch.cuda.synchronize()
+        pairs = max(4, int(math.ceil(min_seconds / max(e0.elapsed_time(e1) / 1e3 / 4, 1e-7))))
+        e0.record(s)
+        for _ in range(pairs):
+            lat.step_between(a, b)
+            lat.step_between(b, a)
+        e1.record(s)
+        torch.cuda.synchronize()
+        dt = e0.elapsed_time(e1) / 1e3 / (2 * pairs)
+        moved = BYTES_PER_UPDATE[storage] * n * n / dt / 1e9
+        out[storage] = {"mlups": round(n * n / dt / 1e6, 1), "launch_us": round(dt * 1e6, 2),
+                        "moved_gbs": round(moved, 1), "moved_frac": round(moved / HBM_PEAK_GBS, 4)}
+        if copy_gbs:
+            out[storage]["moved_vs_copy"] = round(moved / copy_gbs, 4)
+        del lat, a, b
+        torch.cuda.empty_cache()
+    out["workload"] = f"taylor_green_{n}x{n}, one step per launch (lbm_step_between)"
+    return out
+
+
 def copy_calibration(nbytes=1 << 30):
     """A plain elementwise copy kernel of known size (reads and writes nbytes),
     so that counter runs can scale the step kernel's FETCH_SIZE / WRITE_SIZE
@@ -472,8 +516,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
-    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout", "rollout2048"], default=None,
-                    help="time one storage mode, or the forward + adjoint rollout, only (profiling runs)")
+    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout", "rollout2048", "single"],
+                    default=None, help="time one storage mode, the forward + adjoint rollout, or the single-step "
+                    "launches, only (profiling runs)")
     ap.add_argument("--rounding", choices=["nearest", "stochastic"], default="nearest",
                     help="16-bit rounding of an --only fp16/bf16 run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -498,6 +543,9 @@ def main():
     if args.only == "rollout2048":
         print(json.dumps({"only": "rollout2048", **adjoint_rollout(2048, 400, 100)}))
         return
+    if args.only == "single":
+        print(json.dumps({"only": "single", **single_step_rates(copy_gbs=copy_bandwidth())}))
+        return
 
     if args.only in ("fp16", "bf16", "fp64"):
         n = 8192 if args.only != "fp64" else 4096
@@ -514,6 +562,7 @@ def main():
         return
 
     n = args.n
+    copy_gbs = copy_bandwidth()  # first: the GPU leaves idle clocks before the headline's warmup
     lat, tau = cavity_lattice(n, "fp32")
     grp = updates_per_launch("fp32")
     if args.steps < grp:
@@ -530,7 +579,6 @@ def main():
     valu = counter_value("valu_step4_fp32_cavity4096.txt", "valu_wave_instructions_per_launch") if headline else None
     del lat
     torch.cuda.empty_cache()
-    copy_gbs = copy_bandwidth()
     roof = alu_block("fp32", nodes, per_launch)
     roof.update({
         "traffic": None if traffic is None else round(traffic),
@@ -617,6 +665,7 @@ def main():
                               "moved_vs_copy": round(moved16 / copy_gbs, 4)}
                 del l16
                 torch.cuda.empty_cache()
+        forms["single_step"] = single_step_rates(copy_gbs=copy_gbs)
         forms["error_vs_fp64"] = precision_errors()
         forms["error_vs_fp64_tau0.55"] = precision_errors(tau=0.55)
         forms["fwd_adjoint"] = adjoint_rollout()
