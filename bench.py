@@ -12,7 +12,7 @@ two in FP16/BF16).  One JSON line on stdout, also carrying:
   roofline      the dominant kernel, the four-step FP32 launch.  It keeps
                 the intermediate steps on chip and moves 18 B per update, so
                 it is bound by VALU issue, not by HBM: bound "alu", achieved =
-                the method's own operations per launch (97 VALU operations
+                the method's own operations per launch (94 VALU operations
                 per FP32 cell update at the default rates, times the four
                 updates of every node) over the launch's average duration
                 (HIP events between the whole groups and any remainder of K),
@@ -73,11 +73,11 @@ FP32_PEAK_TFLOPS_NONPACKED = 2 * VALU_PEAK_OPS / 1e12  # every lane an FMA: 78.6
 FP32_PEAK_TFLOPS_PUBLISHED = 157.3  # packed FP32 FMA
 # One FP32 cell update of the kernels' factorised collision, without body
 # force and at omega_3 = omega_6 = omega_7 = omega_8 = 1 (their multiplies
-# left out): 97 VALU operations (31 add, 17 sub, 10 mul, 38 fma, 1 rcp), 135
+# left out): 94 VALU operations (30 add, 16 sub, 8 mul, 39 fma, 1 rcp), 133
 # flops with an fma counted as two.  The 16-bit forms add one conversion per
-# population loaded and one per population stored (115).
-COLLISION_OPS = {"fp32": 97, "fp64": 97, "fp16": 115, "bf16": 115}
-COLLISION_FLOPS_FP32 = 135
+# population loaded and one per population stored (112).
+COLLISION_OPS = {"fp32": 94, "fp64": 94, "fp16": 112, "bf16": 112}
+COLLISION_FLOPS_FP32 = 133
 
 
 def updates_per_launch(storage: str) -> int:

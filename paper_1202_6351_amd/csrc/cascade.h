@@ -236,13 +236,10 @@ LBM_HD void populations_T(R ux, R uy, const R Cs[3][3], const R Y[3][3],
 }
 
 // Reciprocal: IEEE division in double; for float the hardware estimate
-// refined by one Newton step (error below 1 ulp, a few instructions instead
-// of the correctly rounded division sequence).
+// (v_rcp_f32, within 1 ulp) instead of the correctly rounded division
+// sequence.
 LBM_HD double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float recip(float x) {
-  const float r = __builtin_amdgcn_rcpf(x);
-  return r * __builtin_fmaf(-x, r, 2.0f);
-}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Hydrodynamic fields from the raw moments of d (Sec. II): rho = rho0 +
 // M_00, u = (M_10 + F_x/2, M_01 + F_y/2)/rho (the rest part has no momentum).
@@ -428,9 +425,9 @@ LBM_HD void collide_step(const Rates<R>& r, R Fx, R Fy, const R d[9], R out[9]) 
   // Relaxation: Delta C = omega (E - C), E the attractors in deviation form.
   const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
   const R q = ux2 + uy2, p = ux2 - uy2;
-  const R as = r.hw3 * fmad(-r.rho0, q, fmad(R(2.0 / 3.0), drho, -(C20 + C02)));
+  const R Es = fmad(-r.rho0, q, fmad(R(2.0 / 3.0), drho, -(C20 + C02)));
   const R ad = r.hw4 * fmad(-r.rho0, p, -(C20 - C02));
-  const R D20 = as + ad, D02 = as - ad;
+  const R D20 = fmad(r.hw3, Es, ad), D02 = fmad(r.hw3, Es, -ad);
   const R E11mC = fmad(-r.rho0, uxy, -C11);
   const R E21mC = fmad(r0uy, ux2 + R(1.0 / 3.0), -C21);
   const R E12mC = fmad(r0ux, uy2 + R(1.0 / 3.0), -C12);

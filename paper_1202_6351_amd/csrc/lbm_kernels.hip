@@ -669,7 +669,7 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
       const int j = j0 + jb, i = t + NT * j;
       if (j < NPT && (NC % NT == 0 || j + 1 < NPT || i < NC)) {
         const uint32_t cy = (uint32_t)i / (uint32_t)EW;
-        const uint32_t off = (base + (uint32_t)i + cy * skip) * (uint32_t)sizeof(S);
+        const uint32_t off = (base + (uint32_t)i + __umul24(cy, skip)) * (uint32_t)sizeof(S);
 #pragma unroll
         for (int k = 0; k < 9; ++k) d[jb][k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
       }
@@ -747,9 +747,13 @@ __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>
   const S* lds = &mid[0][0][0];
   const __amdgpu_buffer_rsrc_t wr = rsrc(dst, g.lattice_bytes);
   const int lx = (int)threadIdx.x & 63;
-  const uint32_t obase = (uint32_t)(y0 * g.pitch + x0 + lx);
+  // byte offset of this thread's first node; each further node lies NT / 64
+  // rows below (a workgroup-uniform stride)
+  uint32_t off = ((uint32_t)(y0 * g.pitch + x0 + lx) + __umul24(threadIdx.x >> 6, (uint32_t)g.pitch)) *
+                 (uint32_t)sizeof(S);
+  const uint32_t stride = (uint32_t)(NT / 64) * (uint32_t)g.pitch * (uint32_t)sizeof(S);
 #pragma unroll
-  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += NT / 64) {
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += NT / 64, off += stride) {
     const int w = (ly + H) * EW + lx + H;
     R d[9];
 #pragma unroll
@@ -760,7 +764,6 @@ __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>
     collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
     S o[9];
     round_out<S, SR>(out, SR ? (uint32_t)((y0 + ly) * g.nx + x0 + lx) : 0u, key, o);
-    const uint32_t off = (obase + (uint32_t)ly * (uint32_t)g.pitch) * (uint32_t)sizeof(S);
     if (g.wb_stores) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(wr, off, g.st_soff[k], o[k]);
