@@ -39,10 +39,12 @@ two in FP16/BF16).  One JSON line on stdout, also carrying:
                 rounding) on Taylor-Green 8192^2 (MLUPS, roofline) with the
                 errors against the FP64 path on Taylor-Green 512^2 after 20k
                 steps at tau 0.8 and 0.55; the forward + adjoint rollout on
-                512 x 512 (T = 2000, checkpoint every 100) and 2048 x 2048
-                (T = 400) with the FP32 gradient's error against the FP64
-                gradient; the adjoint pair launch at 2048^2 on its own, with
-                its HBM roofline (168 B per node and launch).
+                512 x 512 (T = 2000, checkpoint every 100; and with every
+                state kept, so that the backward recomputes nothing) and
+                2048 x 2048 (T = 400) with the FP32 gradient's error against
+                the FP64 gradient; the adjoint pair launch at 2048^2 on its
+                own, with its HBM roofline (168 B per node and launch); the
+                single-step launch in FP32, FP16 and BF16.
 """
 from __future__ import annotations
 
@@ -516,7 +518,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
-    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout", "rollout2048", "single"],
+    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout", "rollout_keep_all", "rollout2048", "single"],
                     default=None, help="time one storage mode, the forward + adjoint rollout, or the single-step "
                     "launches, only (profiling runs)")
     ap.add_argument("--rounding", choices=["nearest", "stochastic"], default="nearest",
@@ -539,6 +541,9 @@ def main():
         copy_calibration()
     if args.only == "rollout":
         print(json.dumps({"only": "rollout", **adjoint_rollout()}))
+        return
+    if args.only == "rollout_keep_all":
+        print(json.dumps({"only": "rollout_keep_all", **adjoint_rollout(512, 2000, 2000)}))
         return
     if args.only == "rollout2048":
         print(json.dumps({"only": "rollout2048", **adjoint_rollout(2048, 400, 100)}))
@@ -669,6 +674,9 @@ def main():
         forms["error_vs_fp64"] = precision_errors()
         forms["error_vs_fp64_tau0.55"] = precision_errors(tau=0.55)
         forms["fwd_adjoint"] = adjoint_rollout()
+        # every state kept (checkpoint interval = T: 2001 FP32 states of 512^2,
+        # 18.9 GB): the backward runs the adjoint only, with no recompute
+        forms["fwd_adjoint_keep_all"] = adjoint_rollout(512, 2000, 2000)
         forms["fwd_adjoint_2048"] = adjoint_rollout(2048, 400, 100)
         forms["adjoint_pair_2048"] = adjoint_pair_roofline(2048, copy_gbs=copy_gbs)
         line["forms"] = forms
