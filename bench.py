@@ -25,7 +25,7 @@ two in FP16/BF16).  One JSON line on stdout, also carrying:
                 launch actually moves and their fraction of 8 TB/s and of the
                 copy bandwidth measured in the same run;
   copy          a plain device-to-device copy of 2 x 2 GiB timed in the run
-                (first, before the headline's lattice is made);
+                (right before the headline's warmup);
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline cavity;
   cpu_plan      the oracle on the other configurations (all host threads and
                 one), the host's copy bandwidth, the CPU model, and the GPU /
@@ -567,11 +567,13 @@ def main():
         return
 
     n = args.n
-    copy_gbs = copy_bandwidth()  # first: the GPU leaves idle clocks before the headline's warmup
     lat, tau = cavity_lattice(n, "fp32")
     grp = updates_per_launch("fp32")
     if args.steps < grp:
         raise SystemExit(f"--steps must be at least {grp} (one fused launch)")
+    # the copy runs right before the headline's warmup, so the GPU has left
+    # its idle clocks when the timed steps start
+    copy_gbs = copy_bandwidth(reps=20)
     dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
     mlups = n * n * args.steps / dt / 1e6
     per_launch = dt_main / launches
