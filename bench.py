@@ -24,15 +24,16 @@ two in FP16/BF16).  One JSON line on stdout, also carrying:
                 8 TB/s (alg_hbm_ratio, above 1 by construction), the bytes the
                 launch actually moves and their fraction of 8 TB/s and of the
                 copy bandwidth measured in the same run;
-  copy          a plain device-to-device copy of 2 x 2 GiB timed in the run
-                (right before the headline's warmup);
+  copy          a plain device-to-device copy of 2 x 2 GiB timed in the run;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline cavity;
   cpu_plan      the oracle on the other configurations (all host threads and
                 one), the host's copy bandwidth, the CPU model, and the GPU /
                 oracle ratio per configuration;
   sizes         the same cavity at 1024^2 and 2048^2 (Re 1000) and 4096^2
-                (Re 5000), FP32, each timed for at least 0.5 s, with the
-                FP32 velocity and strain-rate error against the FP64 path;
+                (Re 5000), FP32, each timed for at least 0.5 s right before
+                the headline (so that the headline is timed in the GPU's
+                settled clock state), with the FP32 velocity and strain-rate
+                error against the FP64 path;
   flows         FP32 Taylor-Green 8192^2 and Poiseuille channels (the
                 256 x 64 configuration and a 8192 x 2048 channel);
   forms         FP16/BF16 deviation storage (nearest and stochastic
@@ -567,14 +568,25 @@ def main():
         return
 
     n = args.n
-    lat, tau = cavity_lattice(n, "fp32")
     grp = updates_per_launch("fp32")
     if args.steps < grp:
         raise SystemExit(f"--steps must be at least {grp} (one fused launch)")
-    # the copy runs right before the headline's warmup, so the GPU has left
-    # its idle clocks when the timed steps start
     copy_gbs = copy_bandwidth(reps=20)
+    forms_on = args.only is None and not args.no_forms
+    lat, tau = cavity_lattice(n, "fp32")
+    size_runs, size_lats = {}, []
+    if forms_on:
+        # The other grids and Reynolds number of the cavity throughput study,
+        # timed first (at least 0.5 s each), with no idle gap before the
+        # headline's warmup: started from idle, the GPU's clock runs through
+        # a power-management transient (launches up to a third slower for
+        # about 30 ms), which a short headline run would otherwise fall in.
+        for ns, re in ((1024, 1000.0), (2048, 1000.0), (4096, 5000.0)):
+            ls, _ = cavity_lattice(ns, "fp32", re)
+            size_runs[(ns, re)] = timed_for(ls, grp)
+            size_lats.append(ls)
     dt, dt_main, launches = timed_steps(lat, args.steps, args.warmup, grp)
+    del size_lats
     mlups = n * n * args.steps / dt / 1e6
     per_launch = dt_main / launches
     nodes = n * n
@@ -620,16 +632,12 @@ def main():
         "copy": {"gbs": copy_gbs, "what": "device-to-device copy, 2 GiB read + 2 GiB written, HIP events"},
         "mass_drift_rel": float(f"{abs(d[0] / nodes - 1.0):.2e}"),
     }
-    if args.only is None and not args.no_forms:
-        # the other grids and Reynolds number of the cavity throughput study
+    if forms_on:
         sizes = {}
-        for ns, re in ((1024, 1000.0), (2048, 1000.0), (4096, 5000.0)):
-            ls, _ = cavity_lattice(ns, "fp32", re)
-            m, pl = timed_for(ls, grp)
+        for (ns, re), (m, pl) in size_runs.items():
             sizes[f"cavity_{ns}x{ns}_re{int(re)}_fp32"] = {
                 "mlups": round(m, 1), "launch_us": round(pl * 1e6, 2), "roofline": alu_block("fp32", ns * ns, pl),
                 "error_vs_fp64": cavity_errors(ns, re, 2000)}
-            del ls
             torch.cuda.empty_cache()
         sizes[f"cavity_{n}x{n}_re1000_fp32"] = {"error_vs_fp64": cavity_errors(n, 1000.0, 2000)}
         line["sizes"] = sizes
