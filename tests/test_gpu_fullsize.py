@@ -117,6 +117,28 @@ def _fused_equals_single(lat, group):
     assert torch.equal(fused, lat.current)
 
 
+@pytest.mark.parametrize("shape", [(1500, 1000), (1408, 1000), (1300, 1250), (4200, 480), (600, 2400)])
+@pytest.mark.parametrize("case", ["cavity", "periodic", "periodic_force", "channel"])
+def test_fp32_four_step_tiles_shapes(shape, case):
+    """FP32 lattices above 1.2 M nodes take four steps per launch on 64 x 24
+    tiles.  Shapes with ragged edges, a pitch equal to the width (1408), few
+    tile rows (4200 x 480) and few tile columns (600 x 2400); walls,
+    periodic sides, uniform force: every launch equals four single steps
+    bit for bit, twice in a row."""
+    from paper_1202_6351_amd import Lattice, Params
+    nx, ny = shape
+    kw = {"cavity": dict(bc=("wall",) * 4, wall_u=(0, 0, 0, 0.1)),
+          "periodic": dict(),
+          "periodic_force": dict(fx=2e-6, fy=-1e-6),
+          "channel": dict(bc=("periodic", "periodic", "wall", "wall"), fx=1e-6)}[case]
+    lat = Lattice(Params(nx, ny, tau=0.6, storage="fp32", **kw), device="cuda:0")
+    lat.init_equilibrium(*W.random_flow(nx, ny, seed=11, u_amp=0.04))
+    lat.step(9)
+    _fused_equals_single(lat, 4)
+    lat.step(5)
+    _fused_equals_single(lat, 4)
+
+
 @pytest.mark.parametrize("storage,group,tol", [("fp32", 4, 4e-7), ("fp32", 3, 4e-7), ("fp64", 4, 6e-15),
                                                ("fp64", 3, 6e-15)])
 def test_cavity_4096_fused_launch(storage, group, tol):
