@@ -77,9 +77,11 @@ FP32_PEAK_TFLOPS_PUBLISHED = 157.3  # packed FP32 FMA
 # One FP32 cell update of the kernels' factorised collision, without body
 # force and at omega_3 = omega_6 = omega_7 = omega_8 = 1 (their multiplies
 # left out): 94 VALU operations (30 add, 16 sub, 8 mul, 39 fma, 1 rcp), 133
-# flops with an fma counted as two.  The 16-bit forms add one conversion per
-# population loaded and one per population stored (112).
-COLLISION_OPS = {"fp32": 94, "fp64": 94, "fp16": 112, "bf16": 112}
+# flops with an fma counted as two.  The 16-bit forms add the conversions:
+# bfloat16 one per population loaded (a shift) and one per population stored
+# (112); binary16 one per population loaded, while eight of the nine stores
+# fold their conversion into the final fma (v_fma_mixlo_f16), so 104.
+COLLISION_OPS = {"fp32": 94, "fp64": 94, "fp16": 104, "bf16": 112}
 COLLISION_FLOPS_FP32 = 133
 
 
