@@ -88,9 +88,10 @@ LBM_HD void ax_mom(R pm, R p0, R pp, R& m0, R& m1, R& m2) {
 }
 template <typename R>
 LBM_HD void ax_mom_T(R a0, R a1, R a2, R& apm, R& ap0, R& app) {
+  const R s = a0 + a2;
   ap0 = a0;
-  apm = a0 - a1 + a2;
-  app = a0 + a1 + a2;
+  apm = s - a1;
+  app = s + a1;
 }
 // Inverse: p0 = m0 - m2, p-+ = (m2 -+ m1)/2.
 template <typename R>
@@ -289,10 +290,11 @@ LBM_HD void collide_adj(const Rates<R>& r, R Fx, R Fy, const R d[9], const R a[9
   const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
   const R tx = third + ux2, ty = third + uy2;
   // increments Delta C = omega (E - C) of the relaxed moments (E: the
-  // attractors in deviation form)
-  const R ds = r.w3 * (fmad(-r0, ux2 + uy2, R(2.0 / 3.0) * drho) - (C20 + C02));
-  const R dd = r.w4 * (-r0 * (ux2 - uy2) - (C20 - C02));
-  const R D20 = R(0.5) * (ds + dd), D02 = R(0.5) * (ds - dd);
+  // attractors in deviation form), the bulk and shear parts of C20, C02
+  // formed as in the step's collision
+  const R Es = fmad(-r0, ux2 + uy2, fmad(R(2.0 / 3.0), drho, -(C20 + C02)));
+  const R dd2 = r.hw4 * fmad(-r0, ux2 - uy2, -(C20 - C02));
+  const R D20 = fmad(r.hw3, Es, dd2), D02 = fmad(r.hw3, Es, -dd2);
   const R D11 = r.w5 * fmad(-r0, uxy, -C11);
   const R D21 = r.w6 * fmad(r0 * uy, tx, -C21);
   const R D12 = r.w7 * fmad(r0 * ux, ty, -C12);
@@ -320,18 +322,22 @@ LBM_HD void collide_adj(const Rates<R>& r, R Fx, R Fy, const R d[9], const R a[9
     aY[1][n] = fmad(ux2x, aMo[2][n], aMo[1][n]);
     aY[0][n] = fmad(ux, fmad(ux, aMo[2][n], aMo[1][n]), aMo[0][n]);
   }
-  R aux = R(2) * (Fx * aMo[2][0]);
-  aux = fmad(Fy, aMo[1][1], fmad(Mo11 + Mo11, aMo[2][1], aux));
-  aux = fmad(Y02, aMo[1][2], fmad(Mo12 + Mo12, aMo[2][2], aux));
+  // the u_x cotangent: hx collects the terms with a factor 2 (added twice
+  // at the end), aux the others; likewise hy and auy for u_y
+  R hx = Fx * aMo[2][0];
+  hx = fmad(Mo11, aMo[2][1], hx);
+  hx = fmad(Mo12, aMo[2][2], hx);
+  R aux = fmad(Y02, aMo[1][2], Fy * aMo[1][1]);
   // y shift by +uy, transposed, per row m (Delta C_m0, Delta C_m1, Delta C_m2)
   const R aD02 = aY[0][2], aD01 = fmad(uy2x, aY[0][2], aY[0][1]);
   const R aD12 = aY[1][2], aD11 = fmad(uy2x, aY[1][2], aY[1][1]);
   const R aD10 = fmad(uy, fmad(uy, aY[1][2], aY[1][1]), aY[1][0]);
   const R aD22 = aY[2][2], aD21 = fmad(uy2x, aY[2][2], aY[2][1]);
   const R aD20 = fmad(uy, fmad(uy, aY[2][2], aY[2][1]), aY[2][0]);
-  R auy = R(2) * (Fy * aY[0][2]);
-  auy = fmad(Fx, aY[1][1], fmad(Y11 + Y11, aY[1][2], auy));
-  auy = fmad(D20, aY[2][1], fmad(Y21 + Y21, aY[2][2], auy));
+  R hy = Fy * aY[0][2];
+  hy = fmad(Y11, aY[1][2], hy);
+  hy = fmad(Y21, aY[2][2], hy);
+  R auy = fmad(D20, aY[2][1], Fx * aY[1][1]);
   aFx += aD10;
   aFy += aD01;
   // relaxation, transposed: the cotangents of E - C per relaxed moment
@@ -340,21 +346,24 @@ LBM_HD void collide_adj(const Rates<R>& r, R Fx, R Fy, const R d[9], const R a[9
   const R aC20 = -(as + adv), aC02 = adv - as;
   R adrho = fmad(R(2.0 / 3.0), as, R(1.0 / 9.0) * a22);
   // attractors: d/d(u_x^2), d/d(u_y^2), d/d(u_x u_y), then the chain to u
-  const R aux2 = fmad(-r0, fmad(ty, a22, as + adv), r0 * uy * a21);
-  const R auy2 = fmad(-r0, fmad(tx, a22, as - adv), r0 * ux * a12);
+  // (as + adv = -aC20, as - adv = -aC02)
+  const R aux2 = fmad(-r0, fmad(ty, a22, -aC20), r0 * uy * a21);
+  const R auy2 = fmad(-r0, fmad(tx, a22, -aC02), r0 * ux * a12);
   const R auxy = -r0 * a11;
   aux = fmad(ux2x, aux2, fmad(uy, auxy, fmad(r0 * ty, a12, aux)));
   auy = fmad(uy2x, auy2, fmad(ux, auxy, fmad(r0 * tx, a21, auy)));
   // y shift to central moments, transposed (aC_00 = aC_10 = aC_01 = 0; the
   // cotangents of C_11, C_21, C_12, C_22 are -a11, -a21, -a12, -a22)
-  const R aX02 = aC02, aX01 = -uy2x * aC02, aX00 = uy * uy * aC02;
+  const R aX02 = aC02, aX01 = -uy2x * aC02, aX00 = uy2 * aC02;
   const R aX12 = -a12, aX11 = fmad(uy2x, a12, -a11);
   const R aX10 = -uy * fmad(uy, a12, -a11);
   const R aX22 = -a22, aX21 = fmad(uy2x, a22, -a21);
   const R aX20 = fmad(-uy, fmad(uy, a22, -a21), aC20);
-  auy = fmad(R(-2) * C01, aC02, auy);
-  auy = fmad(X1[0], a11, fmad(C11 + C11, a12, auy));
-  auy = fmad(X2[0], a21, fmad(C21 + C21, a22, auy));
+  hy = fmad(-C01, aC02, hy);
+  hy = fmad(C11, a12, hy);
+  hy = fmad(C21, a22, hy);
+  auy = fmad(X1[0], a11, auy);
+  auy = fmad(X2[0], a21, auy);
   // x shift to central moments, transposed, per column n
   const R aXc[3][3] = {{aX00, aX01, aX02}, {aX10, aX11, aX12}, {aX20, aX21, aX22}};
   R aM[3][3];
@@ -363,11 +372,14 @@ LBM_HD void collide_adj(const Rates<R>& r, R Fx, R Fy, const R d[9], const R a[9
     aM[2][n] = aXc[2][n];
     aM[1][n] = fmad(-ux2x, aXc[2][n], aXc[1][n]);
     aM[0][n] = fmad(-ux, fmad(-ux, aXc[2][n], aXc[1][n]), aXc[0][n]);
-    aux = fmad(-M[0][n], aXc[1][n], fmad(R(-2) * X1[n], aXc[2][n], aux));
+    aux = fmad(-M[0][n], aXc[1][n], aux);
+    hx = fmad(-X1[n], aXc[2][n], hx);
   }
+  aux = fmad(R(2), hx, aux);
+  auy = fmad(R(2), hy, auy);
   // u = (M_10 + F_x/2, M_01 + F_y/2) / (rho0 + M_00)
   const R ajx = aux * inv, ajy = auy * inv;
-  aM[0][0] += adrho - fmad(ajx, ux, ajy * uy);
+  aM[0][0] = fmad(-ajx, ux, fmad(-ajy, uy, aM[0][0] + adrho));
   aM[1][0] += ajx;
   aM[0][1] += ajy;
   aFx = fmad(R(0.5), ajx, aFx);
