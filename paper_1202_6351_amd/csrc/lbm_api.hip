@@ -108,8 +108,8 @@ void fill_args(const lbm_params* p, int64_t pitch, const void* force, lbm::KArgs
   static const int GY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   const int64_t esz = storage_size(p->storage);
   const int64_t total = 9 * g.plane * esz;
-  // 32-bit byte offsets, and rows short enough for 24-bit multiplies
-  g.fast = total < ((int64_t)1 << 32) && g.pitch < (1 << 24);
+  // 32-bit byte offsets, and rows short enough (in bytes) for 24-bit multiplies
+  g.fast = total < ((int64_t)1 << 32) && g.pitch * esz < (1 << 24);
   g.wb_stores = 2 * total <= lbm::kWriteBackMaxBytes;
   g.lattice_bytes = g.fast ? (uint32_t)total : 0u;
   for (int k = 0; k < 9; ++k) {

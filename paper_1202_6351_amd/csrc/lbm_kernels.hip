@@ -394,8 +394,8 @@ __device__ __forceinline__ bool window_node(const Geom& g, int wx, int wy, int& 
 // The nine populations streaming into node (gx, gy), held in window cell
 // (cx, cy) whose neighbours hold the previous step's post-collision values.
 // WALLS = false: the caller knows that no link of the node crosses a wall.
-template <bool WALLS, typename S, typename R, int EH, int EW>
-__device__ __forceinline__ void pull_window(const KArgs<R>& a, int gx, int gy, const S (&mid)[9][EH][EW],
+template <bool WALLS, typename S, typename R, int EH, int EW, int EHP>
+__device__ __forceinline__ void pull_window(const KArgs<R>& a, int gx, int gy, const S (&mid)[9][EHP][EW],
                                             int cx, int cy, R d[9]) {
   if constexpr (!WALLS) {
 #pragma unroll
@@ -435,11 +435,11 @@ __device__ __forceinline__ void force_at(const KArgs<R>& a, int gx, int gy, R& F
 // kept in LDS.
 // FW: also keep the cell's force in the LDS array fw ([2][EH][EW]) for the
 // later stages.  keep (not null): also store the result there, at (gx, gy).
-template <typename S, int FM, bool SR, int EH, int EW, bool U = false, bool FW = false>
+template <typename S, int FM, bool SR, int EH, int EW, bool U = false, bool FW = false, int EHP>
 __device__ __forceinline__ void collide_into_window(const KArgs<typename Codec<S>::R>& a,
                                                     const Rates<typename Codec<S>::R>& rt, int gx, int gy,
                                                     const typename Codec<S>::R d[9], uint32_t key,
-                                                    S (&mid)[9][EH][EW], int cx, int cy,
+                                                    S (&mid)[9][EHP][EW], int cx, int cy,
                                                     typename Codec<S>::R* fw = nullptr,
                                                     S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
@@ -479,10 +479,10 @@ __device__ __forceinline__ void pull_hbm(const KArgs<typename Codec<S>::R>& a, _
 // unwrapped coordinates) from HBM into LDS, one cell at a time.  fast: no
 // cell of the window pulls across a wall or a wrap, and the lattice is below
 // 4 GiB.
-template <typename S, int FM, bool SR, int EH, int EW, bool U = false>
+template <typename S, int FM, bool SR, int EH, int EW, bool U = false, int EHP>
 __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
-                                               int wx0, int wy0, bool fast, uint32_t key, S (&mid)[9][EH][EW]) {
+                                               int wx0, int wy0, bool fast, uint32_t key, S (&mid)[9][EHP][EW]) {
   using R = typename Codec<S>::R;
   const __amdgpu_buffer_rsrc_t rs = rsrc(src, a.g.lattice_bytes);
   for (int i = (int)threadIdx.x; i < EW * EH; i += 256) {
@@ -501,11 +501,11 @@ __device__ __forceinline__ void stage_from_hbm(const KArgs<typename Codec<S>::R>
 // FW: keep the window's force in fw (see collide_into_window).  KEEP: store
 // the step's result for the tile's nodes (window cells [H, EW - H) x
 // [H, EH - H) inside the domain) to keep.
-template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U = false, bool FW = false, bool KEEP = false>
+template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U = false, bool FW = false, bool KEEP = false, int EHP>
 __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Codec<S>::R>& a,
                                                         const Rates<typename Codec<S>::R>& rt,
                                                         const S* __restrict__ src, int wx0, int wy0, bool fast,
-                                                        uint32_t key, S (&mid)[9][EH][EW],
+                                                        uint32_t key, S (&mid)[9][EHP][EW],
                                                         typename Codec<S>::R* fw = nullptr,
                                                         S* __restrict__ keep = nullptr) {
   constexpr int H = (EW - 64) / 2;
@@ -544,10 +544,10 @@ __device__ __forceinline__ void stage_from_hbm_prefetch(const KArgs<typename Cod
 // FW: forces from fw instead of the force field.  KEEP: store the results of
 // the tile's nodes to keep.
 template <bool WALLS, typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U = false,
-          bool FW = false, bool KEEP = false>
+          bool FW = false, bool KEEP = false, int EHP>
 __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
-                                             uint32_t key, S (&mid)[9][EH][EW],
+                                             uint32_t key, S (&mid)[9][EHP][EW],
                                              const typename Codec<S>::R* fw = nullptr,
                                              S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
@@ -595,10 +595,10 @@ __device__ __forceinline__ void stage_in_lds(const KArgs<typename Codec<S>::R>& 
 // Last stage: one step on the 64 x TY tile from LDS to HBM.
 // FW: forces from fw instead of the force field.
 template <bool WALLS, typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U = false,
-          bool FW = false>
+          bool FW = false, int EHP>
 __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& a,
                                              const Rates<typename Codec<S>::R>& rt, int x0, int y0,
-                                             uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst,
+                                             uint32_t key, const S (&mid)[9][EHP][EW], S* __restrict__ dst,
                                              const typename Codec<S>::R* fw = nullptr) {
   using R = typename Codec<S>::R;
   const Geom& g = a.g;
@@ -633,6 +633,23 @@ __device__ __forceinline__ void stage_to_hbm(const KArgs<typename Codec<S>::R>& 
 // one per-cell offset), every LDS access a per-cell index plus a
 // compile-time offset, and no cell takes a wall or wrap decision.
 
+// Pointer to cell w of the first plane of an LDS window array, opaque to
+// the optimiser: it neither folds part of the cell index into the access
+// offsets nor derives one cell's address from another's, so each cell keeps
+// one base register and its accesses are that base plus an immediate offset.
+template <typename S>
+using LdsPtr = __attribute__((address_space(3))) S*;
+template <typename S>
+__device__ __forceinline__ LdsPtr<S> lds_opaque(LdsPtr<S> p) {
+  uint32_t a = (uint32_t)(uintptr_t)p;
+  asm("" : "+v"(a));
+  return (LdsPtr<S>)(uintptr_t)a;
+}
+template <typename S>
+__device__ __forceinline__ LdsPtr<S> lds_cell(const S* lds, int w) {
+  return lds_opaque((LdsPtr<S>)(lds + w));
+}
+
 // Force of a window cell: none, the uniform one, or the field's.
 template <int FM, typename R>
 __device__ __forceinline__ void core_force(const KArgs<R>& a, int gx, int gy, R& Fx, R& Fy) {
@@ -649,16 +666,18 @@ __device__ __forceinline__ void core_force(const KArgs<R>& a, int gx, int gy, R&
 // First stage: step n on every window cell, from HBM into LDS.  A thread's
 // cells go in batches of B: the loads of a whole batch are issued before its
 // first collision.
-template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U, int B>
+template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U, int B, int EHP>
 __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
-                                               int wx0, int wy0, uint32_t key, S (&mid)[9][EH][EW]) {
+                                               int wx0, int wy0, uint32_t key, S (&mid)[9][EHP][EW]) {
   using R = typename Codec<S>::R;
-  constexpr int NC = EW * EH, NPT = (NC + NT - 1) / NT;
+  constexpr int NC = EW * EH, NPT = (NC + NT - 1) / NT, PL = EHP * EW;
   const Geom& g = a.g;
   const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
-  const uint32_t base = (uint32_t)(wy0 * g.pitch + wx0);  // element index of window cell 0
-  const uint32_t skip = (uint32_t)(g.pitch - EW);
+  // byte offset of this thread's first cell were it in row 0; a cell in
+  // window row cy lies cy (pitch - EW) elements further
+  const uint32_t t0 = (uint32_t)(wy0 * g.pitch + wx0 + (int)threadIdx.x) * (uint32_t)sizeof(S);
+  const uint32_t skip = (uint32_t)(g.pitch - EW) * (uint32_t)sizeof(S);
   S* lds = &mid[0][0][0];
   const int t = (int)threadIdx.x;
 #pragma unroll
@@ -669,7 +688,7 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
       const int j = j0 + jb, i = t + NT * j;
       if (j < NPT && (NC % NT == 0 || j + 1 < NPT || i < NC)) {
         const uint32_t cy = (uint32_t)i / (uint32_t)EW;
-        const uint32_t off = (base + (uint32_t)i + __umul24(cy, skip)) * (uint32_t)sizeof(S);
+        const uint32_t off = t0 + (uint32_t)(NT * j * sizeof(S)) + __umul24(cy, skip);
 #pragma unroll
         for (int k = 0; k < 9; ++k) d[jb][k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
       }
@@ -686,7 +705,7 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
         S o[9];
         round_out<S, SR>(out, SR ? (uint32_t)(gy * g.nx + gx) : 0u, key, o);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) lds[k * NC + i] = o[k];
+        for (int k = 0; k < 9; ++k) lds[k * PL + i] = o[k];
       }
     }
   }
@@ -695,27 +714,30 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
 // Middle stage, in place: one step on the window cells at most RING nodes
 // outside the tile (the window has an H-node ring).  Every thread pulls and
 // collides its cells into registers; after a barrier it writes them back.
-template <typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U>
+template <typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U, int EHP>
 __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
-                                               uint32_t key, S (&mid)[9][EH][EW]) {
+                                               uint32_t key, S (&mid)[9][EHP][EW]) {
   using R = typename Codec<S>::R;
   constexpr int M = H - RING, RW = EW - 2 * M, RH = EH - 2 * M, NC = RW * RH, NPT = (NC + NT - 1) / NT;
-  constexpr int PL = EH * EW;
+  constexpr int PL = EHP * EW;
   S* lds = &mid[0][0][0];
   const int t = (int)threadIdx.x;
   S o[NPT][9];
-  int w[NPT];
+  // the cell in the first eight planes and in the last one (beyond the reach
+  // of an immediate offset), shared by the pulls and the write-back
+  LdsPtr<S> w[NPT], w8[NPT];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int i = t + NT * j;
-    w[j] = 0;
     if (NC % NT == 0 || j + 1 < NPT || i < NC) {
       const int ry = (int)((uint32_t)i / (uint32_t)RW);
-      w[j] = i + ry * (EW - RW) + M * (EW + 1);
+      w[j] = lds_cell(lds, i + ry * (EW - RW) + M * (EW + 1));
+      w8[j] = lds_opaque(w[j] + 8 * PL);
       R d[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(lds[k * PL + w[j] - EY[k] * EW - EX[k]]);
+      for (int k = 0; k < 8; ++k) d[k] = Codec<S>::load(w[j][k * PL - EY[k] * EW - EX[k]]);
+      d[8] = Codec<S>::load(w8[j][-EY[8] * EW - EX[8]]);
       const int gx = wx0 + M + (i - ry * RW), gy = wy0 + M + ry;
       R Fx, Fy;
       core_force<FM>(a, gx, gy, Fx, Fy);
@@ -730,19 +752,20 @@ __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>
     const int i = t + NT * j;
     if (NC % NT == 0 || j + 1 < NPT || i < NC) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) lds[k * PL + w[j]] = o[j][k];
+      for (int k = 0; k < 8; ++k) w[j][k * PL] = o[j][k];
+      *w8[j] = o[j][8];
     }
   }
   __syncthreads();
 }
 
 // Last stage: one step on the 64 x TY tile from LDS to HBM.
-template <typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U>
+template <typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U, int EHP>
 __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, int x0, int y0,
-                                               uint32_t key, const S (&mid)[9][EH][EW], S* __restrict__ dst) {
+                                               uint32_t key, const S (&mid)[9][EHP][EW], S* __restrict__ dst) {
   using R = typename Codec<S>::R;
-  constexpr int PL = EH * EW;
+  constexpr int PL = EHP * EW;
   const Geom& g = a.g;
   const S* lds = &mid[0][0][0];
   const __amdgpu_buffer_rsrc_t wr = rsrc(dst, g.lattice_bytes);
@@ -752,12 +775,16 @@ __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>
   uint32_t off = ((uint32_t)(y0 * g.pitch + x0 + lx) + __umul24(threadIdx.x >> 6, (uint32_t)g.pitch)) *
                  (uint32_t)sizeof(S);
   const uint32_t stride = (uint32_t)(NT / 64) * (uint32_t)g.pitch * (uint32_t)sizeof(S);
+  // TY / (NT / 64) full passes over the tile rows, then a partial one
+  constexpr int RP = NT / 64, NP = (TY + RP - 1) / RP;
 #pragma unroll
-  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += NT / 64, off += stride) {
-    const int w = (ly + H) * EW + lx + H;
+  for (int p = 0; p < NP; ++p, off += stride) {
+    const int ly = (int)(threadIdx.x >> 6) + RP * p;
+    if (TY % RP != 0 && p + 1 == NP && ly >= TY) break;
+    const LdsPtr<S> w = lds_cell(lds, (ly + H) * EW + lx + H);
     R d[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(lds[k * PL + w - EY[k] * EW - EX[k]]);
+    for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(w[k * PL - EY[k] * EW - EX[k]]);
     R Fx, Fy;
     core_force<FM>(a, x0 + lx, y0 + ly, Fx, Fy);
     R out[9];
@@ -772,6 +799,19 @@ __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>
       for (int k = 0; k < 9; ++k) BufIO<S>::store(wr, off, g.st_soff[k], o[k]);
     }
   }
+}
+
+// Rows of a window array in LDS: EH, or up to two more, so that each of the
+// nine planes spans a whole number of 256-byte units, if the array still
+// fits in 80 KB (two workgroups per CU).  Then no two pulls of a cell lie a
+// multiple of 256 bytes apart (none is paired into one two-address LDS read,
+// which costs an address add), while a cell's writes to eight planes pair
+// up from a single address.
+template <typename S, int EH, int EW>
+constexpr int lds_rows() {
+  for (int r = EH; r <= EH + 2; ++r)
+    if (r * EW * (int)sizeof(S) % 256 == 0) return 9 * r * EW * (int)sizeof(S) <= 80 * 1024 ? r : EH;
+  return EH;
 }
 
 // Tile origin of this workgroup; interior: every pull of the window with an
@@ -879,7 +919,7 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
   using R = typename Codec<S>::R;
   constexpr int H = 3, EW = 64 + 2 * H, EH = TY + 2 * H;
   constexpr bool FW = FM == 2 && sizeof(S) == 4 && TY <= 12;
-  __shared__ S mid[9][EH][EW];
+  __shared__ S mid[9][lds_rows<S, EH, EW>()][EW];
   __shared__ R fwin[FW ? 2 * EH * EW : 1];
   R* fw = FW ? fwin : nullptr;
   const auto rt = rates(a);

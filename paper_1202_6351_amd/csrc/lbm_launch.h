@@ -18,7 +18,7 @@ struct Geom {
   // Interior fast path (whole lattice below 4 GiB): byte offset of plane a
   // from the lattice base, for the pull read (shifted by -e_a) and for the
   // store (unshifted).
-  int32_t fast;            // 1 if the byte offsets below fit in 32 bits and the pitch in 24
+  int32_t fast;            // 1 if the byte offsets below fit in 32 bits and a row's bytes in 24
   int32_t wb_stores;       // 1: write-back stores (the lattice pair fits kWriteBackMaxBytes)
   uint32_t lattice_bytes;  // 9 * plane * sizeof(storage) (when fast)
   uint32_t ld_soff[9];
