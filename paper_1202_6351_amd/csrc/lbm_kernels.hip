@@ -760,7 +760,8 @@ __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>
 }
 
 // Last stage: one step on the 64 x TY tile from LDS to HBM.
-template <typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U, int EHP>
+// EDGE: the tile may reach beyond the domain; such nodes are not stored.
+template <typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U, bool EDGE, int EHP>
 __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, int x0, int y0,
                                                uint32_t key, const S (&mid)[9][EHP][EW], S* __restrict__ dst) {
@@ -791,6 +792,7 @@ __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>
     collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
     S o[9];
     round_out<S, SR>(out, SR ? (uint32_t)((y0 + ly) * g.nx + x0 + lx) : 0u, key, o);
+    if (EDGE && (x0 + lx >= g.nx || y0 + ly >= g.ny)) continue;
     if (g.wb_stores) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(wr, off, g.st_soff[k], o[k]);
@@ -798,6 +800,47 @@ __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>
 #pragma unroll
       for (int k = 0; k < 9; ++k) BufIO<S>::store(wr, off, g.st_soff[k], o[k]);
     }
+  }
+}
+
+// Edge tiles in LDS: every window cell c beyond a wall that a node n = c +
+// e_k of the window pulls from gets, in plane k, the value n's bounce-back
+// takes there (its own opposite population plus the wall term, zero where
+// the link crosses two walls), so that the next stage pulls every node as
+// an interior node does.  Storage types of at least 32 bits only: the value
+// is kept exactly as the pull computes it.  One thread per cell of the (at
+// most four) lines of cells just beyond a wall: x_lo, x_hi columns, y_lo,
+// y_hi rows.
+template <typename S, int EH, int EW, int NT, int EHP>
+__device__ __forceinline__ void fill_wall_links(const KArgs<typename Codec<S>::R>& a, int wx0, int wy0,
+                                                S (&mid)[9][EHP][EW]) {
+  static_assert(sizeof(S) >= 4, "the fill keeps the pulled value in the storage type");
+  static_assert(2 * EH + 2 * EW <= NT, "one thread per wall-line cell");
+  using R = typename Codec<S>::R;
+  const Geom& g = a.g;
+  const int t = (int)threadIdx.x;
+  if (t >= 2 * EH + 2 * EW) return;
+  const int line = t < 2 * EH ? t / EH : 2 + (t - 2 * EH) / EW;
+  const int j = t < 2 * EH ? t % EH : (t - 2 * EH) % EW;
+  if (!g.wall[line]) return;
+  const int cx = line < 2 ? (line == 0 ? -1 : g.nx) - wx0 : j;
+  const int cy = line < 2 ? j : (line == 2 ? -1 : g.ny) - wy0;
+  if (cx < 0 || cx >= EW || cy < 0 || cy >= EH) return;
+#pragma unroll
+  for (int k = 1; k < 9; ++k) {
+    // the directions that point from the line into the domain
+    const bool in = line == 0 ? EX[k] == 1 : line == 1 ? EX[k] == -1 : line == 2 ? EY[k] == 1 : EY[k] == -1;
+    const int ncx = cx + EX[k], ncy = cy + EY[k];
+    if (!in || ncx < 0 || ncx >= EW || ncy < 0 || ncy >= EH) continue;
+    int gx, gy;
+    if (!window_node(g, wx0 + ncx, wy0 + ncy, gx, gy)) continue;
+    const Edges e = edges(g, gx, gy);
+    const bool hx = (EX[k] == 1 && e.wxl) || (EX[k] == -1 && e.wxh);
+    const bool hy = (EY[k] == 1 && e.wyl) || (EY[k] == -1 && e.wyh);
+    if (!hx && !hy) continue;
+    const R add = hx == hy ? R(0)
+                           : (hx ? a.wadd[(EX[k] == 1 ? 0 : 1) * 9 + k] : a.wadd[(EY[k] == 1 ? 2 : 3) * 9 + k]);
+    mid[k][cy][cx] = Codec<S>::store(Codec<S>::load(mid[OPP[k]][ncy][ncx]) + add);
   }
 }
 
@@ -845,7 +888,7 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
     if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
       core_stage_hbm<S, FM, SR, EH, EW, 256, U, 2>(a, rt, src, x0 - H, y0 - H, key_a, mid);
       __syncthreads();
-      core_stage_out<S, FM, SR, TY, EH, EW, H, 256, U>(a, rt, x0, y0, key_b, mid, dst);
+      core_stage_out<S, FM, SR, TY, EH, EW, H, 256, U, false>(a, rt, x0, y0, key_b, mid, dst);
       return;
     }
   }
@@ -879,7 +922,7 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
       core_stage_hbm<S, FM, SR, EH, EW, NT, false, 3>(a, rt, src, x0 - H, y0 - H, key_a, mid);
       __syncthreads();
       core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, false>(a, rt, x0 - H, y0 - H, key_b, mid);
-      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, false>(a, rt, x0, y0, key_c, mid, dst);
+      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, false, false>(a, rt, x0, y0, key_c, mid, dst);
       return;
     }
   }
@@ -932,7 +975,26 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
       __syncthreads();
       core_stage_lds<S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
       core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
-      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U>(a, rt, x0, y0, key_d, mid, dst);
+      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U, false>(a, rt, x0, y0, key_d, mid, dst);
+      return;
+    }
+    if (a.g.fast) {  // workgroup-uniform: an edge tile of a lattice below 4 GiB
+      // The first stage pulls through the general gather (walls, wraps);
+      // the later ones run as on interior tiles once the cells beyond each
+      // wall hold the bounce-back values.  Window cells beyond a wall are
+      // computed too (garbage, never pulled by a node: the fill overwrites
+      // what a node pulls from them).
+      stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, U>(a, rt, src, x0 - H, y0 - H, false, key_a, mid);
+      __syncthreads();
+      fill_wall_links<S, EH, EW, NT>(a, x0 - H, y0 - H, mid);
+      __syncthreads();
+      core_stage_lds<S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
+      fill_wall_links<S, EH, EW, NT>(a, x0 - H, y0 - H, mid);
+      __syncthreads();
+      core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
+      fill_wall_links<S, EH, EW, NT>(a, x0 - H, y0 - H, mid);
+      __syncthreads();
+      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U, true>(a, rt, x0, y0, key_d, mid, dst);
       return;
     }
   }
