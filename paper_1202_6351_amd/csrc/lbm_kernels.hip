@@ -978,12 +978,14 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
       core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U, false>(a, rt, x0, y0, key_d, mid, dst);
       return;
     }
-    if (a.g.fast) {  // workgroup-uniform: an edge tile of a lattice below 4 GiB
+    if (TY >= 24 && a.g.fast) {  // workgroup-uniform: an edge tile of a lattice below 4 GiB
       // The first stage pulls through the general gather (walls, wraps);
       // the later ones run as on interior tiles once the cells beyond each
       // wall hold the bounce-back values.  Window cells beyond a wall are
       // computed too (garbage, never pulled by a node: the fill overwrites
-      // what a node pulls from them).
+      // what a node pulls from them).  Tall tiles only: with 8 or 12 rows
+      // (the small lattices, a few workgroups per CU) the three extra
+      // barriers cost more than the interior stages save.
       stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT, U>(a, rt, src, x0 - H, y0 - H, false, key_a, mid);
       __syncthreads();
       fill_wall_links<S, EH, EW, NT>(a, x0 - H, y0 - H, mid);
