@@ -117,14 +117,17 @@ def _fused_equals_single(lat, group):
     assert torch.equal(fused, lat.current)
 
 
-@pytest.mark.parametrize("shape", [(1500, 1000), (1408, 1000), (1300, 1250), (4200, 480), (600, 2400)])
+@pytest.mark.parametrize("shape", [(1500, 1000), (1408, 1000), (1300, 1250), (4200, 480), (600, 2400),
+                                   (150000, 9), (9, 150000)])
 @pytest.mark.parametrize("case", ["cavity", "periodic", "periodic_force", "channel"])
 def test_fp32_four_step_tiles_shapes(shape, case):
     """FP32 lattices above 1.2 M nodes take four steps per launch on 64 x 24
     tiles.  Shapes with ragged edges, a pitch equal to the width (1408), few
-    tile rows (4200 x 480) and few tile columns (600 x 2400); walls,
-    periodic sides, uniform force: every launch equals four single steps
-    bit for bit, twice in a row."""
+    tile rows (4200 x 480) and few tile columns (600 x 2400), and strips
+    narrower than a tile's window (150000 x 9, 9 x 150000: every tile an
+    edge tile, both walls of a pair inside one window, periodic sides
+    wrapping several times); walls, periodic sides, uniform force: every
+    launch equals four single steps bit for bit, twice in a row."""
     from paper_1202_6351_amd import Lattice, Params
     nx, ny = shape
     kw = {"cavity": dict(bc=("wall",) * 4, wall_u=(0, 0, 0, 0.1)),
