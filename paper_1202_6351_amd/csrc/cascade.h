@@ -286,7 +286,7 @@ LBM_HD void collide_adj(const Rates<R>& r, R Fx, R Fy, const R d[9], const R a[9
   const R C12 = fmad(-uy, X1[1] + C11, X1[2]);
   const R C20 = X2[0];
   const R C21 = fmad(-uy, X2[0], X2[1]);
-  const R C22 = fmad(-uy, X2[1] + C21, X2[2]);
+  // (C22 itself is not needed: the step is linear in it)
   const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
   const R tx = third + ux2, ty = third + uy2;
   // increments Delta C = omega (E - C) of the relaxed moments (E: the
