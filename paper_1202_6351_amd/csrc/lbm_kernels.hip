@@ -650,7 +650,9 @@ __device__ __forceinline__ LdsPtr<S> lds_cell(const S* lds, int w) {
   return lds_opaque((LdsPtr<S>)(lds + w));
 }
 
-// Force of a window cell: none, the uniform one, or the field's.
+// Force of a window cell: none, the uniform one, or the field's.  The
+// field ([2][ny][nx], 8 or 16 B per node, so below 4 GiB whenever the
+// lattice is) is read through a buffer descriptor with one 32-bit offset.
 template <int FM, typename R>
 __device__ __forceinline__ void core_force(const KArgs<R>& a, int gx, int gy, R& Fx, R& Fy) {
   Fx = R(0);
@@ -659,7 +661,11 @@ __device__ __forceinline__ void core_force(const KArgs<R>& a, int gx, int gy, R&
     Fx = a.fx;
     Fy = a.fy;
   } else if constexpr (FM == 2) {
-    node_force(a, gx, gy, Fx, Fy);
+    const uint32_t plane = (uint32_t)(a.g.nx * a.g.ny) * (uint32_t)sizeof(R);
+    const __amdgpu_buffer_rsrc_t rf = rsrc(a.force, 2 * plane);
+    const uint32_t off = (uint32_t)(gy * a.g.nx + gx) * (uint32_t)sizeof(R);
+    Fx = BufIO<R>::load(rf, off, 0);
+    Fy = BufIO<R>::load(rf, off, plane);
   }
 }
 
@@ -884,13 +890,11 @@ __global__ __launch_bounds__(256) void k_step2(KArgs<typename Codec<S>::R> a, co
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t2_tiles_x, x0, y0, interior, fast);
-  if constexpr (FM != 2) {
-    if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
-      core_stage_hbm<S, FM, SR, EH, EW, 256, U, 2>(a, rt, src, x0 - H, y0 - H, key_a, mid);
-      __syncthreads();
-      core_stage_out<S, FM, SR, TY, EH, EW, H, 256, U, false>(a, rt, x0, y0, key_b, mid, dst);
-      return;
-    }
+  if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
+    core_stage_hbm<S, FM, SR, EH, EW, 256, U, 2>(a, rt, src, x0 - H, y0 - H, key_a, mid);
+    __syncthreads();
+    core_stage_out<S, FM, SR, TY, EH, EW, H, 256, U, false>(a, rt, x0, y0, key_b, mid, dst);
+    return;
   }
   stage_from_hbm<S, FM, SR, EH, EW, U>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
@@ -917,14 +921,12 @@ __global__ __launch_bounds__(NT) void k_step3(KArgs<typename Codec<S>::R> a, con
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  if constexpr (FM != 2) {
-    if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
-      core_stage_hbm<S, FM, SR, EH, EW, NT, false, 3>(a, rt, src, x0 - H, y0 - H, key_a, mid);
-      __syncthreads();
-      core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, false>(a, rt, x0 - H, y0 - H, key_b, mid);
-      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, false, false>(a, rt, x0, y0, key_c, mid, dst);
-      return;
-    }
+  if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
+    core_stage_hbm<S, FM, SR, EH, EW, NT, false, 3>(a, rt, src, x0 - H, y0 - H, key_a, mid);
+    __syncthreads();
+    core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, false>(a, rt, x0 - H, y0 - H, key_b, mid);
+    core_stage_out<S, FM, SR, TY, EH, EW, H, NT, false, false>(a, rt, x0, y0, key_c, mid, dst);
+    return;
   }
   stage_from_hbm_prefetch<S, FM, SR, EH, EW, NT>(a, rt, src, x0 - H, y0 - H, fast, key_a, mid);
   __syncthreads();
@@ -969,8 +971,9 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  if constexpr (!KEEP && FM != 2) {
+  if constexpr (!KEEP) {
     if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
+      // (a force field is read per stage at the cells' own, unwrapped nodes)
       core_stage_hbm<S, FM, SR, EH, EW, NT, U, 3>(a, rt, src, x0 - H, y0 - H, key_a, mid);
       __syncthreads();
       core_stage_lds<S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
@@ -978,6 +981,8 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
       core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U, false>(a, rt, x0, y0, key_d, mid, dst);
       return;
     }
+  }
+  if constexpr (!KEEP && FM != 2) {
     if (TY >= 24 && a.g.fast) {  // workgroup-uniform: an edge tile of a lattice below 4 GiB
       // The first stage pulls through the general gather (walls, wraps);
       // the later ones run as on interior tiles once the cells beyond each

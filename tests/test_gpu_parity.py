@@ -224,6 +224,31 @@ def test_multi_step_launch_equals_single_steps(storage, rounding, shape, bci, fo
     assert torch.equal(a.populations(), b.populations())
 
 
+@pytest.mark.parametrize("storage,rounding", [("fp64", "nearest"), ("fp32", "nearest"), ("fp16", "nearest"),
+                                              ("bf16", "stochastic")])
+@pytest.mark.parametrize("shape", [(200, 131), (1030, 1030), (1500, 1000)])
+@pytest.mark.parametrize("bci", [0, 3])
+def test_force_field_fused_default_rates(storage, rounding, shape, bci):
+    """A force field with the default rates (omega_6 = omega_7 = omega_8 = 1,
+    the collision variant without those multiplies).  Interior tiles read the
+    field in every stage through a buffer descriptor, edge tiles through the
+    general path; the shapes give FP32 its 64 x 8, 64 x 12 and 64 x 24
+    four-step tiles.  lbm_step(7) equals seven single steps bit for bit."""
+    from paper_1202_6351_amd import Lattice, Params
+    nx, ny = shape
+    bc, wu = BCS[bci]
+    frc = torch.from_numpy(W.force_field(nx, ny, 1e-4, seed=21))
+    kw = dict(tau=0.6, bc=bc, wall_u=wu, storage=storage, rounding=rounding, seed=3)
+    f0 = W.random_populations(nx, ny, seed=17, amp=0.05)
+    a = Lattice(Params(nx, ny, **kw), device="cuda:0", force=frc)
+    a.set_populations(f0).step(7)
+    b = Lattice(Params(nx, ny, **kw), device="cuda:0", force=frc)
+    b.set_populations(f0)
+    for _ in range(7):
+        b.step(1)
+    assert torch.equal(a.populations(), b.populations())
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("bci", [0, 1, 3])
 @pytest.mark.parametrize("force", ["none", "field"])
