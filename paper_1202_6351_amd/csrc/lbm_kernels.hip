@@ -671,13 +671,16 @@ __device__ __forceinline__ void core_force(const KArgs<R>& a, int gx, int gy, R&
 
 // First stage: step n on every window cell, from HBM into LDS.  A thread's
 // cells go in batches of B: the loads of a whole batch are issued before its
-// first collision.
-template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U, int B, int EHP>
+// first collision.  FW: also keep each cell's force in fw ([2][EH][EW]) for
+// the later stages.  KEEP: also store the result of the tile's nodes to keep.
+template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U, int B, bool FW = false, bool KEEP = false,
+          int EHP>
 __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
-                                               int wx0, int wy0, uint32_t key, S (&mid)[9][EHP][EW]) {
+                                               int wx0, int wy0, uint32_t key, S (&mid)[9][EHP][EW],
+                                               typename Codec<S>::R* fw = nullptr, S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
-  constexpr int NC = EW * EH, NPT = (NC + NT - 1) / NT, PL = EHP * EW;
+  constexpr int NC = EW * EH, NPT = (NC + NT - 1) / NT, PL = EHP * EW, H = (EW - 64) / 2;
   const Geom& g = a.g;
   const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
   // byte offset of this thread's first cell were it in row 0; a cell in
@@ -689,29 +692,41 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
 #pragma unroll
   for (int j0 = 0; j0 < NPT; j0 += B) {
     R d[B][9];
+    uint32_t off[B];
 #pragma unroll
     for (int jb = 0; jb < B; ++jb) {
       const int j = j0 + jb, i = t + NT * j;
       if (j < NPT && (NC % NT == 0 || j + 1 < NPT || i < NC)) {
         const uint32_t cy = (uint32_t)i / (uint32_t)EW;
-        const uint32_t off = t0 + (uint32_t)(NT * j * sizeof(S)) + __umul24(cy, skip);
+        off[jb] = t0 + (uint32_t)(NT * j * sizeof(S)) + __umul24(cy, skip);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) d[jb][k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
+        for (int k = 0; k < 9; ++k) d[jb][k] = Codec<S>::load(BufIO<S>::load(rs, off[jb], g.ld_soff[k]));
       }
     }
 #pragma unroll
     for (int jb = 0; jb < B; ++jb) {
       const int j = j0 + jb, i = t + NT * j;
       if (j < NPT && (NC % NT == 0 || j + 1 < NPT || i < NC)) {
-        const int cy = i / EW, gx = wx0 + (i - cy * EW), gy = wy0 + cy;
+        const int cy = i / EW, cx = i - cy * EW, gx = wx0 + cx, gy = wy0 + cy;
         R Fx, Fy;
         core_force<FM>(a, gx, gy, Fx, Fy);
+        if constexpr (FW) {
+          fw[i] = Fx;
+          fw[EH * EW + i] = Fy;
+        }
         R out[9];
         collide_step<R, FM != 0, U>(rt, Fx, Fy, d[jb], out);
         S o[9];
         round_out<S, SR>(out, SR ? (uint32_t)(gy * g.nx + gx) : 0u, key, o);
 #pragma unroll
         for (int k = 0; k < 9; ++k) lds[k * PL + i] = o[k];
+        if constexpr (KEEP) {
+          if (cx >= H && cx < EW - H && cy >= H && cy < EH - H) {
+            const __amdgpu_buffer_rsrc_t rk = rsrc(keep, g.lattice_bytes);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(rk, off[jb], g.st_soff[k], o[k]);
+          }
+        }
       }
     }
   }
@@ -720,10 +735,15 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
 // Middle stage, in place: one step on the window cells at most RING nodes
 // outside the tile (the window has an H-node ring).  Every thread pulls and
 // collides its cells into registers; after a barrier it writes them back.
-template <typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U, int EHP>
+// FW: forces from fw.  KEEP: also store the result of the tile's nodes to
+// keep (after the write-back; no load follows in the launch but LDS ones).
+template <typename S, int FM, bool SR, int EH, int EW, int H, int RING, int NT, bool U, bool FW = false,
+          bool KEEP = false, int EHP>
 __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, int wx0, int wy0,
-                                               uint32_t key, S (&mid)[9][EHP][EW]) {
+                                               uint32_t key, S (&mid)[9][EHP][EW],
+                                               const typename Codec<S>::R* fw = nullptr,
+                                               S* __restrict__ keep = nullptr) {
   using R = typename Codec<S>::R;
   constexpr int M = H - RING, RW = EW - 2 * M, RH = EH - 2 * M, NC = RW * RH, NPT = (NC + NT - 1) / NT;
   constexpr int PL = EHP * EW;
@@ -737,8 +757,8 @@ __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>
   for (int j = 0; j < NPT; ++j) {
     const int i = t + NT * j;
     if (NC % NT == 0 || j + 1 < NPT || i < NC) {
-      const int ry = (int)((uint32_t)i / (uint32_t)RW);
-      w[j] = lds_cell(lds, i + ry * (EW - RW) + M * (EW + 1));
+      const int ry = (int)((uint32_t)i / (uint32_t)RW), c = i + ry * (EW - RW) + M * (EW + 1);
+      w[j] = lds_cell(lds, c);
       w8[j] = lds_opaque(w[j] + 8 * PL);
       R d[9];
 #pragma unroll
@@ -746,7 +766,12 @@ __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>
       d[8] = Codec<S>::load(w8[j][-EY[8] * EW - EX[8]]);
       const int gx = wx0 + M + (i - ry * RW), gy = wy0 + M + ry;
       R Fx, Fy;
-      core_force<FM>(a, gx, gy, Fx, Fy);
+      if constexpr (FW) {
+        Fx = fw[c];
+        Fy = fw[EH * EW + c];
+      } else {
+        core_force<FM>(a, gx, gy, Fx, Fy);
+      }
       R out[9];
       collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
       round_out<S, SR>(out, SR ? (uint32_t)(gy * a.g.nx + gx) : 0u, key, o[j]);
@@ -760,6 +785,15 @@ __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>
 #pragma unroll
       for (int k = 0; k < 8; ++k) w[j][k * PL] = o[j][k];
       *w8[j] = o[j][8];
+      if constexpr (KEEP) {
+        const int ry = (int)((uint32_t)i / (uint32_t)RW), cx = M + (i - ry * RW), cy = M + ry;
+        if (cx >= H && cx < EW - H && cy >= H && cy < EH - H) {
+          const __amdgpu_buffer_rsrc_t rk = rsrc(keep, a.g.lattice_bytes);
+          const uint32_t off = (uint32_t)((wy0 + cy) * a.g.pitch + wx0 + cx) * (uint32_t)sizeof(S);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) BufIO<S>::template store<0>(rk, off, a.g.st_soff[k], o[j][k]);
+        }
+      }
     }
   }
   __syncthreads();
@@ -767,10 +801,13 @@ __device__ __forceinline__ void core_stage_lds(const KArgs<typename Codec<S>::R>
 
 // Last stage: one step on the 64 x TY tile from LDS to HBM.
 // EDGE: the tile may reach beyond the domain; such nodes are not stored.
-template <typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U, bool EDGE, int EHP>
+// FW: forces from fw.
+template <typename S, int FM, bool SR, int TY, int EH, int EW, int H, int NT, bool U, bool EDGE, bool FW = false,
+          int EHP>
 __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, int x0, int y0,
-                                               uint32_t key, const S (&mid)[9][EHP][EW], S* __restrict__ dst) {
+                                               uint32_t key, const S (&mid)[9][EHP][EW], S* __restrict__ dst,
+                                               const typename Codec<S>::R* fw = nullptr) {
   using R = typename Codec<S>::R;
   constexpr int PL = EHP * EW;
   const Geom& g = a.g;
@@ -788,12 +825,18 @@ __device__ __forceinline__ void core_stage_out(const KArgs<typename Codec<S>::R>
   for (int p = 0; p < NP; ++p, off += stride) {
     const int ly = (int)(threadIdx.x >> 6) + RP * p;
     if (TY % RP != 0 && p + 1 == NP && ly >= TY) break;
-    const LdsPtr<S> w = lds_cell(lds, (ly + H) * EW + lx + H);
+    const int c = (ly + H) * EW + lx + H;
+    const LdsPtr<S> w = lds_cell(lds, c);
     R d[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(w[k * PL - EY[k] * EW - EX[k]]);
     R Fx, Fy;
-    core_force<FM>(a, x0 + lx, y0 + ly, Fx, Fy);
+    if constexpr (FW) {
+      Fx = fw[c];
+      Fy = fw[EH * EW + c];
+    } else {
+      core_force<FM>(a, x0 + lx, y0 + ly, Fx, Fy);
+    }
     R out[9];
     collide_step<R, FM != 0, U>(rt, Fx, Fy, d, out);
     S o[9];
@@ -971,14 +1014,20 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
   int x0, y0;
   bool interior, fast;
   tile_origin<TY, H>(a.g, a.g.t3_tiles_x, x0, y0, interior, fast);
-  if constexpr (!KEEP) {
+  // State-keeping launches take the interior path only where no later stage
+  // loads from memory after the first kept store: no force field, or its
+  // window held in LDS.
+  if constexpr (!KEEP || FM != 2 || FW) {
     if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
-      // (a force field is read per stage at the cells' own, unwrapped nodes)
-      core_stage_hbm<S, FM, SR, EH, EW, NT, U, 3>(a, rt, src, x0 - H, y0 - H, key_a, mid);
+      // (a force field is read at the cells' own, unwrapped nodes: in every
+      // stage, or once into fw)
+      core_stage_hbm<S, FM, SR, EH, EW, NT, U, 3, FW, KEEP>(a, rt, src, x0 - H, y0 - H, key_a, mid, fw, keep0);
       __syncthreads();
-      core_stage_lds<S, FM, SR, EH, EW, H, 2, NT, U>(a, rt, x0 - H, y0 - H, key_b, mid);
-      core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, U>(a, rt, x0 - H, y0 - H, key_c, mid);
-      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U, false>(a, rt, x0, y0, key_d, mid, dst);
+      core_stage_lds<S, FM, SR, EH, EW, H, 2, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_b, mid, fw, keep1);
+      if (KEEP && !keep2) return;
+      core_stage_lds<S, FM, SR, EH, EW, H, 1, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_c, mid, fw, keep2);
+      if (KEEP && !dst) return;
+      core_stage_out<S, FM, SR, TY, EH, EW, H, NT, U, false, FW>(a, rt, x0, y0, key_d, mid, dst, fw);
       return;
     }
   }

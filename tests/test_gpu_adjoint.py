@@ -492,16 +492,22 @@ def test_rollout_forward_same_with_and_without_gradient(storage, T, every):
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("bci", [0, 2])
 @pytest.mark.parametrize("n", [6, 7])
-@pytest.mark.parametrize("shape", [(1030, 1030), (1500, 1000)])
-def test_step_sequence_large_shape(storage, bci, n, shape):
-    """lbm_step_sequence on 1030 x 1030 and 1500 x 1000 (FP32 takes its
-    64 x 12 and 64 x 24 four-step tiles that keep their states: a group of
-    four, then one launch cut short after two or three steps; FP64 runs
-    single steps), periodic or walls and lid, force field: the kept states
-    equal as many lbm_step_between calls bit for bit."""
+@pytest.mark.parametrize("shape", [(300, 200), (1030, 1030), (1500, 1000)])
+@pytest.mark.parametrize("force", ["field", "none"])
+def test_step_sequence_large_shape(storage, bci, n, shape, force):
+    """lbm_step_sequence on 300 x 200, 1030 x 1030 and 1500 x 1000 (FP32
+    takes its 64 x 8, 64 x 12 and 64 x 24 four-step tiles that keep their
+    states, interior tiles included: a group of four, then one launch cut
+    short after two or three steps; FP64 runs single steps), periodic or
+    walls and lid, with a force field or none: the kept states equal as many
+    lbm_step_between calls bit for bit."""
+    from paper_1202_6351_amd import Lattice, Params
     nx, ny = shape
     bc, wu = BCS[bci]
-    lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=12), storage=storage, tau=0.6, bc=bc, wall_u=wu)
+    if force == "field":
+        lat = _lattice(nx, ny, W.force_field(nx, ny, 1e-4, seed=12), storage=storage, tau=0.6, bc=bc, wall_u=wu)
+    else:
+        lat = Lattice(Params(nx, ny, storage=storage, tau=0.6, bc=bc, wall_u=wu), device=DEV)
     lat.set_populations(W.random_populations(nx, ny, seed=13, amp=0.05))
     src = lat.snapshot()
     seq = [lat.new_lattice() for _ in range(n)]
