@@ -376,15 +376,23 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, con
 // unassigned on some path, the compiler (ROCm 7.2, gfx950) has zeroed gx for
 // all lanes of the y-wrap branch, the lanes that wrapped among them, when the
 // results went into per-thread arrays of three cells.
+// A coordinate wrapped into [0, n): one period off in all but windows wider
+// than the lattice, so the remainder (an integer division) is the rare case.
+__device__ __forceinline__ int wrap_coord(int w, int n) {
+  w += w < 0 ? n : (w >= n ? -n : 0);
+  if (w < 0 || w >= n) w = ((w % n) + n) % n;
+  return w;
+}
+
 __device__ __forceinline__ bool window_node(const Geom& g, int wx, int wy, int& gx, int& gy) {
   bool ok = true;
   if (wx < 0 || wx >= g.nx) {
     ok = g.wall[wx < 0 ? 0 : 1] == 0;
-    wx = ((wx % g.nx) + g.nx) % g.nx;
+    wx = wrap_coord(wx, g.nx);
   }
   if (wy < 0 || wy >= g.ny) {
     ok = ok & (g.wall[wy < 0 ? 2 : 3] == 0);
-    wy = ((wy % g.ny) + g.ny) % g.ny;
+    wy = wrap_coord(wy, g.ny);
   }
   gx = wx;
   gy = wy;
