@@ -105,100 +105,6 @@ __device__ __forceinline__ NodePos node_pos(const Geom& g) {
   return p;
 }
 
-// Neighbour coordinates with periodic wrap and the wall flags of a node.
-struct Edges {
-  int xm, xp, ym, yp;      // x-1, x+1, y-1, y+1 wrapped
-  bool wxl, wxh, wyl, wyh;  // node touches the x_lo / x_hi / y_lo / y_hi wall
-};
-
-__device__ __forceinline__ Edges edges(const Geom& g, int x, int y) {
-  Edges e;
-  e.xm = x == 0 ? g.nx - 1 : x - 1;
-  e.xp = x == g.nx - 1 ? 0 : x + 1;
-  e.ym = y == 0 ? g.ny - 1 : y - 1;
-  e.yp = y == g.ny - 1 ? 0 : y + 1;
-  e.wxl = (x == 0) && g.wall[0];
-  e.wxh = (x == g.nx - 1) && g.wall[1];
-  e.wyl = (y == 0) && g.wall[2];
-  e.wyh = (y == g.ny - 1) && g.wall[3];
-  return e;
-}
-
-// Where the population streaming into (x, y) along direction A comes from:
-// element offset into the lattice and the moving-wall term.  Fluid or
-// periodic link: plane A at (x - e_x, y - e_y).  Link crossing a wall
-// (halfway bounce-back): plane opp(A) at (x, y), plus 6 rho0 w_A (e_A .
-// U_wall) of that wall (precomputed per side and direction in wadd).  A link
-// crossing two walls passes through their corner point, which is at rest:
-// plain bounce-back, no wall term.
-template <int A, typename R>
-__device__ __forceinline__ int64_t link_src(const Geom& g, const Edges& e, int x, int y,
-                                            const R* wadd, R& add) {
-  constexpr int ex = EX[A], ey = EY[A];
-  const bool hx = (ex == 1 && e.wxl) || (ex == -1 && e.wxh);
-  const bool hy = (ey == 1 && e.wyl) || (ey == -1 && e.wyh);
-  const int sx = ex == 1 ? e.xm : (ex == -1 ? e.xp : x);
-  const int sy = ey == 1 ? e.ym : (ey == -1 ? e.yp : y);
-  add = hx == hy ? R(0) : (hx ? wadd[(ex == 1 ? 0 : 1) * 9 + A] : wadd[(ey == 1 ? 2 : 3) * 9 + A]);
-  const bool hit = hx || hy;
-  const int plane = hit ? OPP[A] : A;
-  const int off = hit ? y * g.pitch + x : sy * g.pitch + sx;
-  return (int64_t)plane * g.plane + off;
-}
-
-template <typename S, typename R>
-__device__ __forceinline__ void gather(const Geom& g, const R* wadd, const S* __restrict__ src,
-                                       int x, int y, R d[9]) {
-  const Edges e = edges(g, x, y);
-#define LBM_GATHER(A)                                          \
-  {                                                            \
-    R add;                                                     \
-    const int64_t i = link_src<A, R>(g, e, x, y, wadd, add);   \
-    d[A] = Codec<S>::load(src[i]) + add;                       \
-  }
-  LBM_GATHER(0) LBM_GATHER(1) LBM_GATHER(2) LBM_GATHER(3) LBM_GATHER(4)
-  LBM_GATHER(5) LBM_GATHER(6) LBM_GATHER(7) LBM_GATHER(8)
-#undef LBM_GATHER
-}
-
-// Inverse of gather(): write the pre-collision value v[a] of (x, y) to the
-// place the next gather reads it from (minus the wall term).  Every lattice
-// element is written exactly once over all nodes (streaming is a
-// permutation).
-template <typename S, typename R>
-__device__ __forceinline__ void scatter(const Geom& g, const R* wadd, S* __restrict__ dst, int x,
-                                        int y, const R v[9], bool subtract_wall) {
-  const Edges e = edges(g, x, y);
-#define LBM_SCATTER(A)                                          \
-  {                                                             \
-    R add;                                                      \
-    const int64_t i = link_src<A, R>(g, e, x, y, wadd, add);    \
-    dst[i] = Codec<S>::store(subtract_wall ? v[A] - add : v[A]); \
-  }
-  LBM_SCATTER(0) LBM_SCATTER(1) LBM_SCATTER(2) LBM_SCATTER(3) LBM_SCATTER(4)
-  LBM_SCATTER(5) LBM_SCATTER(6) LBM_SCATTER(7) LBM_SCATTER(8)
-#undef LBM_SCATTER
-}
-
-template <typename R>
-__device__ __forceinline__ void node_force(const KArgs<R>& a, int x, int y, R& Fx, R& Fy) {
-  if (a.force) {
-    const int64_t c = (int64_t)y * a.g.nx + x;
-    Fx = a.force[c];
-    Fy = a.force[(int64_t)a.g.nx * a.g.ny + c];
-  } else {
-    Fx = a.fx;
-    Fy = a.fy;
-  }
-}
-
-template <typename R>
-__device__ __forceinline__ Rates<R> rates(const KArgs<R>& a) {
-  return make_rates<R>(a.w, a.rho0);
-}
-
-// ------------------------------------------------------------------ kernels
-
 // Buffer-resource access for the interior fast path.  One descriptor covers
 // a whole lattice; plane a is reached through a scalar offset (soffset) that
 // already includes its streaming shift, so a wavefront addresses all nine
@@ -252,6 +158,126 @@ template <> struct BufIO<__bf16> {
                                           CP);
   }
 };
+
+// Neighbour coordinates with periodic wrap and the wall flags of a node.
+struct Edges {
+  int xm, xp, ym, yp;      // x-1, x+1, y-1, y+1 wrapped
+  bool wxl, wxh, wyl, wyh;  // node touches the x_lo / x_hi / y_lo / y_hi wall
+};
+
+__device__ __forceinline__ Edges edges(const Geom& g, int x, int y) {
+  Edges e;
+  e.xm = x == 0 ? g.nx - 1 : x - 1;
+  e.xp = x == g.nx - 1 ? 0 : x + 1;
+  e.ym = y == 0 ? g.ny - 1 : y - 1;
+  e.yp = y == g.ny - 1 ? 0 : y + 1;
+  e.wxl = (x == 0) && g.wall[0];
+  e.wxh = (x == g.nx - 1) && g.wall[1];
+  e.wyl = (y == 0) && g.wall[2];
+  e.wyh = (y == g.ny - 1) && g.wall[3];
+  return e;
+}
+
+// Where the population streaming into (x, y) along direction A comes from:
+// element offset into the lattice and the moving-wall term.  Fluid or
+// periodic link: plane A at (x - e_x, y - e_y).  Link crossing a wall
+// (halfway bounce-back): plane opp(A) at (x, y), plus 6 rho0 w_A (e_A .
+// U_wall) of that wall (precomputed per side and direction in wadd).  A link
+// crossing two walls passes through their corner point, which is at rest:
+// plain bounce-back, no wall term.
+template <int A, typename R>
+__device__ __forceinline__ int64_t link_src(const Geom& g, const Edges& e, int x, int y,
+                                            const R* wadd, R& add) {
+  constexpr int ex = EX[A], ey = EY[A];
+  const bool hx = (ex == 1 && e.wxl) || (ex == -1 && e.wxh);
+  const bool hy = (ey == 1 && e.wyl) || (ey == -1 && e.wyh);
+  const int sx = ex == 1 ? e.xm : (ex == -1 ? e.xp : x);
+  const int sy = ey == 1 ? e.ym : (ey == -1 ? e.yp : y);
+  add = hx == hy ? R(0) : (hx ? wadd[(ex == 1 ? 0 : 1) * 9 + A] : wadd[(ey == 1 ? 2 : 3) * 9 + A]);
+  const bool hit = hx || hy;
+  const int plane = hit ? OPP[A] : A;
+  const int off = hit ? y * g.pitch + x : sy * g.pitch + sx;
+  return (int64_t)plane * g.plane + off;
+}
+
+// BUF: on a lattice below 4 GiB, read the same sources through a buffer
+// descriptor (32-bit element offsets from three row offsets, no 64-bit
+// address arithmetic per link): the forward step's edge nodes and window
+// cells.  (The adjoint's gathers measured slower that way and keep the flat
+// loads.)
+template <typename S, typename R, bool BUF = false>
+__device__ __forceinline__ void gather(const Geom& g, const R* wadd, const S* __restrict__ src,
+                                       int x, int y, R d[9]) {
+  const Edges e = edges(g, x, y);
+  if (BUF && g.fast) {
+    const __amdgpu_buffer_rsrc_t rs = rsrc(src, g.lattice_bytes);
+    const uint32_t rm = (uint32_t)(e.ym * g.pitch), r0 = (uint32_t)(y * g.pitch), rp = (uint32_t)(e.yp * g.pitch);
+#define LBM_GATHER_B(A)                                                                                     \
+    {                                                                                                       \
+      constexpr int ex = EX[A], ey = EY[A];                                                                 \
+      const bool hx = (ex == 1 && e.wxl) || (ex == -1 && e.wxh);                                            \
+      const bool hy = (ey == 1 && e.wyl) || (ey == -1 && e.wyh);                                            \
+      const R add = hx == hy ? R(0)                                                                         \
+                             : (hx ? wadd[(ex == 1 ? 0 : 1) * 9 + A] : wadd[(ey == 1 ? 2 : 3) * 9 + A]);    \
+      const uint32_t sx = (uint32_t)(ex == 1 ? e.xm : (ex == -1 ? e.xp : x));                               \
+      const uint32_t sr = ey == 1 ? rm : (ey == -1 ? rp : r0);                                              \
+      const uint32_t off = (hx || hy) ? r0 + (uint32_t)x + (uint32_t)(OPP[A] * g.plane)                     \
+                                      : sr + sx + (uint32_t)(A * g.plane);                                  \
+      d[A] = Codec<S>::load(BufIO<S>::load(rs, off * (uint32_t)sizeof(S), 0)) + add;                        \
+    }
+    LBM_GATHER_B(0) LBM_GATHER_B(1) LBM_GATHER_B(2) LBM_GATHER_B(3) LBM_GATHER_B(4)
+    LBM_GATHER_B(5) LBM_GATHER_B(6) LBM_GATHER_B(7) LBM_GATHER_B(8)
+#undef LBM_GATHER_B
+    return;
+  }
+#define LBM_GATHER(A)                                          \
+  {                                                            \
+    R add;                                                     \
+    const int64_t i = link_src<A, R>(g, e, x, y, wadd, add);   \
+    d[A] = Codec<S>::load(src[i]) + add;                       \
+  }
+  LBM_GATHER(0) LBM_GATHER(1) LBM_GATHER(2) LBM_GATHER(3) LBM_GATHER(4)
+  LBM_GATHER(5) LBM_GATHER(6) LBM_GATHER(7) LBM_GATHER(8)
+#undef LBM_GATHER
+}
+
+// Inverse of gather(): write the pre-collision value v[a] of (x, y) to the
+// place the next gather reads it from (minus the wall term).  Every lattice
+// element is written exactly once over all nodes (streaming is a
+// permutation).
+template <typename S, typename R>
+__device__ __forceinline__ void scatter(const Geom& g, const R* wadd, S* __restrict__ dst, int x,
+                                        int y, const R v[9], bool subtract_wall) {
+  const Edges e = edges(g, x, y);
+#define LBM_SCATTER(A)                                          \
+  {                                                             \
+    R add;                                                      \
+    const int64_t i = link_src<A, R>(g, e, x, y, wadd, add);    \
+    dst[i] = Codec<S>::store(subtract_wall ? v[A] - add : v[A]); \
+  }
+  LBM_SCATTER(0) LBM_SCATTER(1) LBM_SCATTER(2) LBM_SCATTER(3) LBM_SCATTER(4)
+  LBM_SCATTER(5) LBM_SCATTER(6) LBM_SCATTER(7) LBM_SCATTER(8)
+#undef LBM_SCATTER
+}
+
+template <typename R>
+__device__ __forceinline__ void node_force(const KArgs<R>& a, int x, int y, R& Fx, R& Fy) {
+  if (a.force) {
+    const int64_t c = (int64_t)y * a.g.nx + x;
+    Fx = a.force[c];
+    Fy = a.force[(int64_t)a.g.nx * a.g.ny + c];
+  } else {
+    Fx = a.fx;
+    Fy = a.fy;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ Rates<R> rates(const KArgs<R>& a) {
+  return make_rates<R>(a.w, a.rho0);
+}
+
+// ------------------------------------------------------------------ kernels
 
 // The nine stored values of node (x, y) into lattice dst.  Non-temporal
 // stores stream a large lattice past the caches; a lattice whose pair fits in
@@ -343,7 +369,7 @@ __global__ __launch_bounds__(256) void k_step(KArgs<typename Codec<S>::R> a, con
 #pragma unroll
     for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(r, off, g.ld_soff[k]));
   } else {
-    gather<S, R>(g, a.wadd, src, p.x, p.y, d);
+    gather<S, R, true>(g, a.wadd, src, p.x, p.y, d);
   }
   R Fx = R(0), Fy = R(0);
   if (FM == 1) {
@@ -479,7 +505,7 @@ __device__ __forceinline__ void pull_hbm(const KArgs<typename Codec<S>::R>& a, _
 #pragma unroll
     for (int k = 0; k < 9; ++k) d[k] = Codec<S>::load(BufIO<S>::load(rs, off, g.ld_soff[k]));
   } else {
-    gather<S, R>(g, a.wadd, src, gx, gy, d);
+    gather<S, R, true>(g, a.wadd, src, gx, gy, d);
   }
 }
 
