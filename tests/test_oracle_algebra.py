@@ -4,6 +4,7 @@ No GPU.  Each test checks the oracle against something the paper or the
 mathematics fixes independently of the oracle's own formulas.
 """
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -12,7 +13,13 @@ import oracle
 from tests import plain
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-RNG = np.random.default_rng(1234)
+
+
+@pytest.fixture
+def rng(request):
+    # One generator per test, seeded by the test's name, so that a test's
+    # draws do not depend on which tests ran before it in the same process.
+    return np.random.default_rng(zlib.crc32(request.node.name.encode()))
 
 
 def _random_case(rng, u_amp=0.1, f_amp=1e-2):
@@ -49,12 +56,12 @@ def test_k_orthogonality_diagonal():
     np.testing.assert_array_equal(K.T @ K, np.diag([9, 6, 6, 36, 4, 4, 12, 12, 36]).astype(float))
 
 
-def test_equilibrium_central_moments():
+def test_equilibrium_central_moments(rng):
     """f^eq has the Maxwellian central moments (rho, 0, 0, c_s^2 rho, c_s^2 rho,
     0, 0, 0, c_s^4 rho) of Sec. II, and equals the product closed form."""
     for _ in range(20):
-        rho = RNG.uniform(0.8, 1.2)
-        ux, uy = RNG.uniform(-0.2, 0.2, 2)
+        rho = rng.uniform(0.8, 1.2)
+        ux, uy = rng.uniform(-0.2, 0.2, 2)
         feq = oracle.equilibrium(rho, ux, uy)
         C = plain.central_moments(feq, ux, uy)
         want = np.array([rho, 0, 0, rho / 3, rho / 3, 0, 0, 0, rho / 9])
@@ -62,12 +69,12 @@ def test_equilibrium_central_moments():
         np.testing.assert_allclose(feq, plain.feq_product(rho, ux, uy), rtol=0, atol=1e-15)
 
 
-def test_source_central_moments():
+def test_source_central_moments(rng):
     """The discrete source S_a has central moments (0, F_x, F_y, 0, ..., 0)
     (Sec. II, Galilean invariance matching of sources), for any u."""
     for _ in range(20):
-        fx, fy = RNG.uniform(-1e-2, 1e-2, 2)
-        ux, uy = RNG.uniform(-0.2, 0.2, 2)
+        fx, fy = rng.uniform(-1e-2, 1e-2, 2)
+        ux, uy = rng.uniform(-0.2, 0.2, 2)
         S = oracle.source(fx, fy, ux, uy)
         C = plain.central_moments(S, ux, uy)
         np.testing.assert_allclose(C, [0, fx, fy, 0, 0, 0, 0, 0, 0], rtol=0, atol=1e-16)
@@ -99,36 +106,36 @@ def test_collide_equals_central_moment_relaxation(seed):
         np.testing.assert_allclose(got, want, rtol=0, atol=2e-15)
 
 
-def test_collide_fixed_point_of_equilibrium():
+def test_collide_fixed_point_of_equilibrium(rng):
     """C(f^eq - S/2) = f^eq + S/2 for any rates: the transformed equilibrium
     is left unchanged by relaxation and gains the full source."""
     for _ in range(20):
-        rho = RNG.uniform(0.9, 1.1)
-        ux, uy = RNG.uniform(-0.1, 0.1, 2)
-        fx, fy = RNG.uniform(-1e-3, 1e-3, 2)
+        rho = rng.uniform(0.9, 1.1)
+        ux, uy = rng.uniform(-0.1, 0.1, 2)
+        fx, fy = rng.uniform(-1e-3, 1e-3, 2)
         om = np.zeros(9)
-        om[3:9] = RNG.uniform(0.1, 1.9, 6)
+        om[3:9] = rng.uniform(0.1, 1.9, 6)
         feq = plain.feq_product(rho, ux, uy)
         S = oracle.source(fx, fy, ux, uy)
         np.testing.assert_allclose(oracle.collide(om, fx, fy, feq - S / 2), feq + S / 2,
                                    rtol=0, atol=1e-15)
 
 
-def test_collide_projection_at_unit_rates():
+def test_collide_projection_at_unit_rates(rng):
     """With all rates 1 (tau = 1) any input maps to f^eq(rho, u) + S/2."""
     om = np.zeros(9)
     om[3:9] = 1.0
     for _ in range(20):
-        f, fx, fy, _ = _random_case(RNG)
+        f, fx, fy, _ = _random_case(rng)
         rho, ux, uy = plain.fields(f, fx, fy)
         want = plain.feq_product(rho, ux, uy) + oracle.source(fx, fy, ux, uy) / 2
         np.testing.assert_allclose(oracle.collide(om, fx, fy, f), want, rtol=0, atol=2e-15)
 
 
-def test_collide_conserves_mass_and_adds_force():
+def test_collide_conserves_mass_and_adds_force(rng):
     """sum f~ = sum f and sum f~ e = sum f e + F (g0 = g1 = g2 = 0, Sec. II)."""
     for _ in range(50):
-        f, fx, fy, om = _random_case(RNG)
+        f, fx, fy, om = _random_case(rng)
         out = oracle.collide(om, fx, fy, f)
         assert abs(out.sum() - f.sum()) < 2e-15
         assert abs(out @ plain.EX - (f @ plain.EX + fx)) < 2e-15
@@ -150,12 +157,14 @@ def test_collide_unforced_zero_velocity_second_order_relaxation():
     assert abs((out @ (plain.EX * plain.EY)) - (1 - 1.25) * 4e-3) < 1e-16
 
 
-def test_x_mirror_equivariance_per_node():
+def test_x_mirror_equivariance_per_node(rng):
     """Mirroring x (swap E<->W, NE<->NW, SW<->SE, F_x -> -F_x) commutes with
-    the collision."""
+    the collision.  Exact in exact arithmetic; in FP64 the mirrored input is
+    summed in another order, so the two sides differ by a few ulps of the
+    largest population (a wrong sign on any x-odd term gives ~1e-3)."""
     perm = [0, 3, 2, 1, 4, 6, 5, 8, 7]
     for _ in range(20):
-        f, fx, fy, om = _random_case(RNG)
+        f, fx, fy, om = _random_case(rng)
         a = oracle.collide(om, fx, fy, f)[perm]
         b = oracle.collide(om, -fx, fy, f[perm])
-        np.testing.assert_allclose(a, b, rtol=0, atol=2e-16)
+        np.testing.assert_allclose(a, b, rtol=0, atol=8 * np.finfo(float).eps * np.abs(a).max())
