@@ -1309,7 +1309,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(KArgs<typename Codec<S>::R
 // every node the tile touches and its neighbours lie inside the domain, so
 // the pulls, the reverse streaming and the window lookups need no wall or
 // wrap handling.
-template <bool WALLS, typename S, int TY>
+template <bool WALLS, typename S, int TY, int NT>
 __device__ __forceinline__ void adjoint_pair_tile(const KArgs<typename Codec<S>::R>& a, int x0, int y0,
                                                   const S* __restrict__ prev_a, const S* __restrict__ prev_b,
                                                   const typename Codec<S>::R* __restrict__ mu_in,
@@ -1324,7 +1324,7 @@ __device__ __forceinline__ void adjoint_pair_tile(const KArgs<typename Codec<S>:
   const int wx0 = x0 - H, wy0 = y0 - H;
   // ---- stage 1: adjoint of step n on the tile and a one-node ring
   constexpr int RW = EW - 2, RH = EH - 2;
-  for (int i = (int)threadIdx.x; i < RW * RH; i += 256) {
+  for (int i = (int)threadIdx.x; i < RW * RH; i += NT) {
     const int cx = 1 + i % RW, cy = 1 + i / RW;
     int gx = wx0 + cx, gy = wy0 + cy;
     if (WALLS && !window_node(g, wx0 + cx, wy0 + cy, gx, gy)) continue;
@@ -1363,7 +1363,7 @@ __device__ __forceinline__ void adjoint_pair_tile(const KArgs<typename Codec<S>:
   __syncthreads();
   // ---- stage 2: adjoint of step n-1 on the tile
   const int lx = (int)threadIdx.x & 63;
-  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += 4) {
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += NT / 64) {
     const int gx = x0 + lx, gy = y0 + ly;
     if (gx >= g.nx || gy >= g.ny) continue;
     R d[9];
@@ -1397,12 +1397,13 @@ __device__ __forceinline__ void adjoint_pair_tile(const KArgs<typename Codec<S>:
 // same sums in the same order as two single adjoint steps, so the result is
 // bit-for-bit theirs.  HBM per node and two steps: mu in and out, both
 // states, force and gradient once -- 168 B (FP32) against 264.
-template <typename S, int TY>
-__global__ __launch_bounds__(256) void k_adjoint_step2(KArgs<typename Codec<S>::R> a, const S* __restrict__ prev_a,
+template <typename S, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adjoint_step2(KArgs<typename Codec<S>::R> a, const S* __restrict__ prev_a,
                                                        const S* __restrict__ prev_b,
                                                        const typename Codec<S>::R* __restrict__ mu_in,
                                                        typename Codec<S>::R* __restrict__ mu_out,
                                                        typename Codec<S>::R* __restrict__ grad_force) {
+  static_assert(NT % 64 == 0 && NT <= 1024, "whole wavefronts");
   using R = typename Codec<S>::R;
   __shared__ R mid[9][TY + 4][68];  // cotangent of state n on the window (two-node ring)
   __shared__ R aF1[2][TY][64];      // stage 1 force cotangents of the tile
@@ -1413,9 +1414,9 @@ __global__ __launch_bounds__(256) void k_adjoint_step2(KArgs<typename Codec<S>::
   // domain's edge rows or columns means no wall link and no wrap anywhere
   const bool inner = x0 >= 2 && x0 + 66 <= g.nx && y0 >= 2 && y0 + TY + 2 <= g.ny;
   if (inner)  // workgroup-uniform
-    adjoint_pair_tile<false, S, TY>(a, x0, y0, prev_a, prev_b, mu_in, mu_out, grad_force, mid, aF1);
+    adjoint_pair_tile<false, S, TY, NT>(a, x0, y0, prev_a, prev_b, mu_in, mu_out, grad_force, mid, aF1);
   else
-    adjoint_pair_tile<true, S, TY>(a, x0, y0, prev_a, prev_b, mu_in, mu_out, grad_force, mid, aF1);
+    adjoint_pair_tile<true, S, TY, NT>(a, x0, y0, prev_a, prev_b, mu_in, mu_out, grad_force, mid, aF1);
 }
 
 // Adjoint of the macroscopic map rho, u at lattice lat.
@@ -1737,23 +1738,23 @@ hipError_t launch_adjoint_step2(const KArgsAny& a, const void* prev_a, const voi
   const Geom& g = a.g();
   switch (a.storage) {
     case 0: {
-      constexpr int TY = kAdjoint2TyF64;
+      constexpr int TY = kAdjoint2TyF64, NT = kAdjoint2ThreadsF64;
       const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
-      hipLaunchKernelGGL((k_adjoint_step2<double, TY>), grid, dim3(256), 0, st, a.d, (const double*)prev_a,
+      hipLaunchKernelGGL((k_adjoint_step2<double, TY, NT>), grid, dim3(NT), 0, st, a.d, (const double*)prev_a,
                          (const double*)prev_b, (const double*)mu_in, (double*)mu_out, (double*)grad_force);
       return hipGetLastError();
     }
     case 1: {
       if ((int64_t)g.nx * g.ny <= kAdjoint2SmallMaxNodes) {
-        constexpr int TY = kAdjoint2TyF32Small;
+        constexpr int TY = kAdjoint2TyF32Small, NT = kAdjoint2ThreadsF32Small;
         const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
-        hipLaunchKernelGGL((k_adjoint_step2<float, TY>), grid, dim3(256), 0, st, a.f, (const float*)prev_a,
+        hipLaunchKernelGGL((k_adjoint_step2<float, TY, NT>), grid, dim3(NT), 0, st, a.f, (const float*)prev_a,
                            (const float*)prev_b, (const float*)mu_in, (float*)mu_out, (float*)grad_force);
         return hipGetLastError();
       }
-      constexpr int TY = kAdjoint2TyF32;
+      constexpr int TY = kAdjoint2TyF32, NT = kAdjoint2ThreadsF32;
       const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
-      hipLaunchKernelGGL((k_adjoint_step2<float, TY>), grid, dim3(256), 0, st, a.f, (const float*)prev_a,
+      hipLaunchKernelGGL((k_adjoint_step2<float, TY, NT>), grid, dim3(NT), 0, st, a.f, (const float*)prev_a,
                          (const float*)prev_b, (const float*)mu_in, (float*)mu_out, (float*)grad_force);
       return hipGetLastError();
     }

@@ -61,12 +61,17 @@ constexpr int kStep4TyF64 = 8, kStep4ThreadsF64 = 512;
 // this many nodes.
 constexpr int64_t kStep2SmallMaxNodes = (int64_t)1 << 21;
 
-// Two-step adjoint tile heights (64 x TY tiles, 256 threads).
-constexpr int kAdjoint2TyF32 = 8, kAdjoint2TyF64 = 4;
-// FP32 lattices of up to kAdjoint2SmallMaxNodes nodes take 64 x 4 tiles, twice
-// the workgroups (measured at 512^2: 7.17 -> 6.6 us per adjoint step, the
-// rollout's backward 22.8 -> 21.4 ms; slower from 1024^2 up).
-constexpr int kAdjoint2TyF32Small = 4;
+// Two-step adjoint tiles: 64 x TY nodes, NT threads (a multiple of 64).
+constexpr int kAdjoint2TyF32 = 8, kAdjoint2ThreadsF32 = 256;
+constexpr int kAdjoint2TyF64 = 4, kAdjoint2ThreadsF64 = 256;
+// FP32 lattices of up to kAdjoint2SmallMaxNodes nodes take 512-thread
+// workgroups, so that a thread has at most two cells in the first stage and
+// one node in the second (three and two with 256 threads on 64 x 8 tiles; two
+// and one on 64 x 4, but with 27 % ring cells against 14 %).  Measured at
+// 512^2: 64 x 8 / 256 threads 7.2 us per adjoint step, 64 x 4 / 256 6.9,
+// 64 x 8 / 512 6.7; the FP32 rollout (T = 2000, checkpoint 100) 26.0 ->
+// 24.8 ms against 64 x 4.  From 1024^2 up 256 threads are as fast.
+constexpr int kAdjoint2TyF32Small = 8, kAdjoint2ThreadsF32Small = 512;
 constexpr int64_t kAdjoint2SmallMaxNodes = 600000;
 
 // Kernel arguments in the compute real R.
