@@ -233,9 +233,9 @@ def test_rollout_finite_differences_32():
 
 # (nx, ny, T, checkpoint interval, storage, tolerance relative to the largest
 # reference gradient entry).  16 x 14 has no tile away from the domain's
-# edges; on 136 x 24 the adjoint pairs (64 x 4 tiles) run their wall-free
-# form on the tiles at x0 = 64, y0 = 4 .. 16, and the forward its four-step
-# tiles (64 x 8).  FP32 bound: the FP32 forward and adjoint accumulate
+# edges; on 136 x 24 the adjoint pairs run their wall-free form on the tiles
+# at x0 = 64, y0 = 4 .. 16 in FP64 (64 x 4 tiles) and at x0 = 64, y0 = 8 in
+# FP32 (64 x 8), and the forward its four-step tiles (64 x 8).  FP32 bound: the FP32 forward and adjoint accumulate
 # rounding of order 1e-7 per step over T = 20 steps; measured errors are
 # about 1e-6 of the largest entry.
 AUTOGRAD_CASES = [
@@ -355,13 +355,15 @@ def test_sequences_equal_single_calls(storage, n, bci, shape):
     assert torch.equal(gf_a, gf_b)
 
 
+@pytest.mark.parametrize("shape", [(801, 800), (512, 512), (700, 511)])
 @pytest.mark.parametrize("bci", range(len(BCS)))
-def test_adjoint_pairs_large_tiles(bci):
-    """FP32 adjoint pairs on 64 x 8 tiles (lattices above 600 000 nodes;
-    smaller ones take 64 x 4): 801 x 800, ragged in x, five steps (two pairs
-    and a single step) equal five single adjoint steps, grad_force included,
-    bit for bit."""
-    nx, ny, n = 801, 800, 5
+def test_adjoint_pairs_large_tiles(bci, shape):
+    """FP32 adjoint pairs on 64 x 8 tiles, with 256 threads on lattices above
+    600 000 nodes (801 x 800, ragged in x) and 512 threads below (512 x 512,
+    the rollout benchmark's launch; 700 x 511, ragged in x and y): five
+    steps (two pairs and a single step) equal five single adjoint steps,
+    grad_force included, bit for bit."""
+    (nx, ny), n = shape, 5
     bc, wu = BCS[bci]
     frc = W.force_field(nx, ny, 1e-4, seed=6)
     lat = _lattice(nx, ny, frc, storage="fp32", tau=0.7, omega3=1.1, bc=bc, wall_u=wu)
