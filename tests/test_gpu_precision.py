@@ -79,8 +79,9 @@ def test_stochastic_rounding_restart_bit_exact():
     assert torch.equal(full, c.populations())
 
 
+@pytest.mark.parametrize("regime", ["normal", "subnormal"])
 @pytest.mark.parametrize("plane", range(9))
-def test_stochastic_rounding_is_unbiased(plane):
+def test_stochastic_rounding_is_unbiased(plane, regime):
     """One step of a uniform flow on a periodic lattice: every node computes
     the same FP32 post-collision value v of each population (checked with an
     FP32 lattice started from the very same stored state), and stochastic
@@ -89,12 +90,14 @@ def test_stochastic_rounding_is_unbiased(plane):
     standard error is 1/1000 ulp).  Every population draws its random bits
     from a different part of the generator, so each one is checked.  The
     density and velocity put every deviation between 4e-4 and 8e-3, in
-    FP16's normal range; below 2^-14 the FP16 store rounds to nearest."""
+    FP16's normal range, or (subnormal) below 2^-14, where the step between
+    FP16 neighbours is 2^-24 and the rounding must stay unbiased too."""
     from paper_1202_6351_amd import Lattice, Params
     n = 512
-    rho = np.full((n, n), 1.006)
-    ux = np.full((n, n), 0.02)
-    uy = np.full((n, n), -0.013)
+    d_rho, u_x, u_y = (0.006, 0.02, -0.013) if regime == "normal" else (1.1e-5, 4e-6, -3e-6)
+    rho = np.full((n, n), 1.0 + d_rho)
+    ux = np.full((n, n), u_x)
+    uy = np.full((n, n), u_y)
     lat = Lattice(Params(n, n, tau=0.8, storage="fp16", rounding="stochastic", seed=1), device="cuda:0")
     lat.init_equilibrium(rho, ux, uy)
     f0 = lat.populations()
@@ -109,4 +112,7 @@ def test_stochastic_rounding_is_unbiased(plane):
     vals = np.unique(stored)
     assert len(vals) == 2 and vals[0] < v < vals[1], (vals, v)
     ulp = vals[1] - vals[0]
+    w = (4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36)[plane]
+    if regime == "subnormal":
+        assert abs(v - w) < 2.0 ** -14 and abs(ulp - 2.0 ** -24) < 1e-3 * 2.0 ** -24, (v - w, ulp)
     assert abs(stored.mean() - v) < 0.01 * ulp
