@@ -548,10 +548,19 @@ lbm_status lbm_adjoint_sequence(lbm_ctx* c, const void* const* states, int64_t n
   for (int64_t i = 0; i < n; ++i)
     if (!states[i]) return inval(c, "adjoint_sequence: states[i] is NULL");
   if (grad_force && !c->has_force_field) return inval(c, "adjoint_sequence: grad_force needs a bound force field");
-  // Pairs of steps run as one two-step adjoint launch; an odd one alone.
+  // On large FP32 lattices groups of four steps run as one four-step adjoint
+  // launch; then pairs of steps as one two-step launch; an odd one alone.
   void* mu[2] = {mu_a, mu_b};
   int k = 0;
   int64_t i = n - 1;
+  const bool quads = c->p.storage == LBM_FP32 && c->p.nx >= 128 && c->p.ny >= 64 &&
+                     (int64_t)c->p.nx * c->p.ny >= lbm::kAdjoint4MinNodes;
+  for (; quads && i >= 3; i -= 4, k ^= 1) {
+    lbm_status s = dev_err(c, lbm::launch_adjoint_step4(c->args, states[i], states[i - 1], states[i - 2],
+                                                        states[i - 3], mu[k], mu[k ^ 1], grad_force, c->stream),
+                           "four-step adjoint kernel");
+    if (s != LBM_OK) return s;
+  }
   for (; i >= 1; i -= 2, k ^= 1) {
     lbm_status s = dev_err(c, lbm::launch_adjoint_step2(c->args, states[i], states[i - 1], mu[k], mu[k ^ 1],
                                                         grad_force, c->stream),

@@ -1431,6 +1431,192 @@ __global__ __launch_bounds__(NT) void k_adjoint_step2(KArgs<typename Codec<S>::R
     adjoint_pair_tile<true, S, TY, NT>(a, x0, y0, prev_a, prev_b, mu_in, mu_out, grad_force, mid, aF1);
 }
 
+// Four adjoint steps per launch (FP32 lattices of kAdjoint4MinNodes nodes or
+// more).  The window array holds the cotangents of a 64 x TY tile and a
+// four-node ring.  Stage 1 runs the adjoint of step n on the cells within
+// three nodes of the tile (mu_in from HBM) and scatters its reverse-streamed
+// result into the window, as the pair's first stage does.  Stages 2 and 3
+// run the adjoints of steps n-1 and n-2 on the cells within two and one
+// nodes, in place: every thread reads its cells' nine cotangents and
+// computes, then after a barrier scatters.  A window position receives each
+// plane from exactly one cell, and the positions a stage reads get all nine
+// planes from the stage before.  Stage 4 runs the adjoint of step n-3 on the
+// tile and scatters to mu_out.  The force gradient of a tile node is carried
+// in acc as ((g + a_n) + a_(n-1)) + a_(n-2), then + a_(n-3): the sums of four
+// single adjoint steps in their order, so the launch equals them bit for
+// bit.  HBM per node and four steps: four states 144 B, cotangent in and out
+// 72, force 8, gradient read and written 16 -- 240 B against 336 for two
+// pair launches.
+
+// Reverse streaming of cell (cx, cy) of node (gx, gy) into the window.
+template <bool WALLS, typename R, int EH, int EW>
+__device__ __forceinline__ void adjoint_win_scatter(const Geom& g, R (&win)[9][EH][EW], int cx, int cy, int gx,
+                                                    int gy, const R nu[9]) {
+  if constexpr (WALLS) {
+    const Edges e = edges(g, gx, gy);
+#define LBM_SCATTER_WIN4(A)                                                       \
+    {                                                                             \
+      constexpr int sx = EX[A], sy = EY[A];                                       \
+      const bool hx = (sx == 1 && e.wxl) || (sx == -1 && e.wxh);                  \
+      const bool hy = (sy == 1 && e.wyl) || (sy == -1 && e.wyh);                  \
+      if (hx || hy) win[OPP[A]][cy][cx] = nu[A];                                  \
+      else win[A][cy - sy][cx - sx] = nu[A];                                      \
+    }
+    LBM_SCATTER_WIN4(0) LBM_SCATTER_WIN4(1) LBM_SCATTER_WIN4(2) LBM_SCATTER_WIN4(3) LBM_SCATTER_WIN4(4)
+    LBM_SCATTER_WIN4(5) LBM_SCATTER_WIN4(6) LBM_SCATTER_WIN4(7) LBM_SCATTER_WIN4(8)
+#undef LBM_SCATTER_WIN4
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) win[k][cy - EY[k]][cx - EX[k]] = nu[k];
+  }
+}
+
+// One in-place middle stage of the four-step adjoint: the cells at least M
+// cells inside the window (M = 2: within two nodes of the tile; M = 3: one).
+template <bool WALLS, typename S, int TY, int NT, int M>
+__device__ __forceinline__ void adjoint_quad_mid(const KArgs<typename Codec<S>::R>& a,
+                                                 const Rates<typename Codec<S>::R>& r, int x0, int y0,
+                                                 const S* __restrict__ prev, bool grad,
+                                                 typename Codec<S>::R (&win)[9][TY + 8][72],
+                                                 typename Codec<S>::R (&acc)[2][TY][64]) {
+  using R = typename Codec<S>::R;
+  constexpr int H = 4, EW = 72, EH = TY + 8, RW = EW - 2 * M, RH = EH - 2 * M, NC = RW * RH;
+  constexpr int NPT = (NC + NT - 1) / NT;
+  const Geom& g = a.g;
+  const int wx0 = x0 - H, wy0 = y0 - H;
+  R nu[NPT][9];
+  int gxs[NPT], gys[NPT];
+  bool live[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int i = (int)threadIdx.x + NT * j;
+    const int cx = M + i % RW, cy = M + i / RW;
+    int gx = wx0 + cx, gy = wy0 + cy;
+    live[j] = i < NC;
+    if (WALLS && live[j]) live[j] = window_node(g, wx0 + cx, wy0 + cy, gx, gy);
+    gxs[j] = gx;
+    gys[j] = gy;
+    if (!live[j]) continue;
+    R d[9];
+    if constexpr (WALLS) gather<S, R>(g, a.wadd, prev, gx, gy, d);
+    else gather_inner<S, R>(g, prev, gx, gy, d);
+    R Fx, Fy;
+    node_force(a, gx, gy, Fx, Fy);
+    R mu[9], ax = R(0), ay = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mu[k] = win[k][cy][cx];
+    collide_adj(r, Fx, Fy, d, mu, nu[j], ax, ay);
+    const int lx = cx - H, ly = cy - H;
+    if (grad && lx >= 0 && lx < 64 && ly >= 0 && ly < TY) {
+      acc[0][ly][lx] = acc[0][ly][lx] + ax;
+      acc[1][ly][lx] = acc[1][ly][lx] + ay;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    if (!live[j]) continue;
+    const int i = (int)threadIdx.x + NT * j;
+    const int cx = M + i % RW, cy = M + i / RW;
+    adjoint_win_scatter<WALLS, R, EH, EW>(g, win, cx, cy, gxs[j], gys[j], nu[j]);
+  }
+  __syncthreads();
+}
+
+template <bool WALLS, typename S, int TY, int NT>
+__device__ __forceinline__ void adjoint_quad_tile(const KArgs<typename Codec<S>::R>& a, int x0, int y0,
+                                                  const S* __restrict__ prev_a, const S* __restrict__ prev_b,
+                                                  const S* __restrict__ prev_c, const S* __restrict__ prev_d,
+                                                  const typename Codec<S>::R* __restrict__ mu_in,
+                                                  typename Codec<S>::R* __restrict__ mu_out,
+                                                  typename Codec<S>::R* __restrict__ grad_force,
+                                                  typename Codec<S>::R (&win)[9][TY + 8][72],
+                                                  typename Codec<S>::R (&acc)[2][TY][64]) {
+  using R = typename Codec<S>::R;
+  constexpr int H = 4, EW = 72, EH = TY + 8;
+  const Geom& g = a.g;
+  const Rates<R> r = rates(a);
+  const int wx0 = x0 - H, wy0 = y0 - H;
+  const bool grad = grad_force != nullptr;
+  // ---- stage 1: adjoint of step n on the cells within three nodes of the tile
+  {
+    constexpr int RW = EW - 2, RH = EH - 2;
+    for (int i = (int)threadIdx.x; i < RW * RH; i += NT) {
+      const int cx = 1 + i % RW, cy = 1 + i / RW;
+      int gx = wx0 + cx, gy = wy0 + cy;
+      if (WALLS && !window_node(g, wx0 + cx, wy0 + cy, gx, gy)) continue;
+      R d[9];
+      if constexpr (WALLS) gather<S, R>(g, a.wadd, prev_a, gx, gy, d);
+      else gather_inner<S, R>(g, prev_a, gx, gy, d);
+      R Fx, Fy;
+      node_force(a, gx, gy, Fx, Fy);
+      const int64_t c = (int64_t)gy * g.pitch + gx;
+      R mu[9], nu[9], ax = R(0), ay = R(0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) mu[k] = mu_in[(int64_t)k * g.plane + c];
+      collide_adj(r, Fx, Fy, d, mu, nu, ax, ay);
+      adjoint_win_scatter<WALLS, R, EH, EW>(g, win, cx, cy, gx, gy, nu);
+      const int lx = cx - H, ly = cy - H;
+      if (grad && lx >= 0 && lx < 64 && ly >= 0 && ly < TY && x0 + lx < g.nx && y0 + ly < g.ny) {
+        const int64_t cf = (int64_t)gy * g.nx + gx;
+        acc[0][ly][lx] = grad_force[cf] + ax;
+        acc[1][ly][lx] = grad_force[(int64_t)g.nx * g.ny + cf] + ay;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- stages 2 and 3, in place
+  adjoint_quad_mid<WALLS, S, TY, NT, 2>(a, r, x0, y0, prev_b, grad, win, acc);
+  adjoint_quad_mid<WALLS, S, TY, NT, 3>(a, r, x0, y0, prev_c, grad, win, acc);
+  // ---- stage 4: adjoint of step n-3 on the tile, to mu_out
+  const int lx = (int)threadIdx.x & 63;
+  for (int ly = (int)threadIdx.x >> 6; ly < TY; ly += NT / 64) {
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= g.nx || gy >= g.ny) continue;
+    R d[9];
+    if constexpr (WALLS) gather<S, R>(g, a.wadd, prev_d, gx, gy, d);
+    else gather_inner<S, R>(g, prev_d, gx, gy, d);
+    R Fx, Fy;
+    node_force(a, gx, gy, Fx, Fy);
+    R mu[9], nu[9], ax = R(0), ay = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mu[k] = win[k][ly + H][lx + H];
+    collide_adj(r, Fx, Fy, d, mu, nu, ax, ay);
+    if constexpr (WALLS) scatter<R, R>(g, a.wadd, mu_out, gx, gy, nu, false);
+    else scatter_inner<R>(g, mu_out, gx, gy, nu);
+    if (grad) {
+      const int64_t cf = (int64_t)gy * g.nx + gx;
+      grad_force[cf] = acc[0][ly][lx] + ax;
+      grad_force[(int64_t)g.nx * g.ny + cf] = acc[1][ly][lx] + ay;
+    }
+  }
+}
+
+template <typename S, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adjoint_step4(KArgs<typename Codec<S>::R> a, const S* __restrict__ prev_a,
+                                                      const S* __restrict__ prev_b, const S* __restrict__ prev_c,
+                                                      const S* __restrict__ prev_d,
+                                                      const typename Codec<S>::R* __restrict__ mu_in,
+                                                      typename Codec<S>::R* __restrict__ mu_out,
+                                                      typename Codec<S>::R* __restrict__ grad_force) {
+  static_assert(NT % 64 == 0 && NT <= 1024, "whole wavefronts");
+  using R = typename Codec<S>::R;
+  __shared__ R win[9][TY + 8][72];  // cotangents on the window (four-node ring)
+  __shared__ R acc[2][TY][64];      // running force gradient of the tile's nodes
+  const Geom& g = a.g;
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int x0 = (tile % g.t2_tiles_x) * 64, y0 = (tile / g.t2_tiles_x) * TY;
+  // stage 1 nodes span [x0 - 3, x0 + 66] x [y0 - 3, y0 + TY + 2]; none on the
+  // domain's edge rows or columns means no wall link and no wrap anywhere
+  const bool inner = x0 >= 4 && x0 + 68 <= g.nx && y0 >= 4 && y0 + TY + 4 <= g.ny;
+  if (inner)  // workgroup-uniform
+    adjoint_quad_tile<false, S, TY, NT>(a, x0, y0, prev_a, prev_b, prev_c, prev_d, mu_in, mu_out, grad_force, win,
+                                        acc);
+  else
+    adjoint_quad_tile<true, S, TY, NT>(a, x0, y0, prev_a, prev_b, prev_c, prev_d, mu_in, mu_out, grad_force, win,
+                                       acc);
+}
+
 // Adjoint of the macroscopic map rho, u at lattice lat.
 template <typename S>
 __global__ __launch_bounds__(256) void k_adjoint_macro(KArgs<typename Codec<S>::R> a, const S* __restrict__ lat,
@@ -1773,6 +1959,19 @@ hipError_t launch_adjoint_step2(const KArgsAny& a, const void* prev_a, const voi
     default:
       return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_adjoint_step4(const KArgsAny& a, const void* prev_a, const void* prev_b, const void* prev_c,
+                                const void* prev_d, const void* mu_in, void* mu_out, void* grad_force,
+                                hipStream_t st) {
+  const Geom& g = a.g();
+  if (a.storage != 1) return hipErrorInvalidValue;
+  constexpr int TY = kAdjoint4Ty, NT = kAdjoint4Threads;
+  const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
+  hipLaunchKernelGGL((k_adjoint_step4<float, TY, NT>), grid, dim3(NT), 0, st, a.f, (const float*)prev_a,
+                     (const float*)prev_b, (const float*)prev_c, (const float*)prev_d, (const float*)mu_in,
+                     (float*)mu_out, (float*)grad_force);
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint_step(const KArgsAny& a, const void* prev, const void* mu_in, void* mu_out,

@@ -73,6 +73,11 @@ constexpr int kAdjoint2TyF64 = 4, kAdjoint2ThreadsF64 = 256;
 // 24.8 ms against 64 x 4.  From 1024^2 up 256 threads are as fast.
 constexpr int kAdjoint2TyF32Small = 8, kAdjoint2ThreadsF32Small = 512;
 constexpr int64_t kAdjoint2SmallMaxNodes = 600000;
+// Four-step adjoint (FP32 only): 64 x TY tiles, NT threads, used for groups
+// of four steps on lattices of at least kAdjoint4MinNodes nodes that are at
+// least 128 x 64 (below that the pairs' shorter latency chain wins).
+constexpr int kAdjoint4Ty = 16, kAdjoint4Threads = 512;
+constexpr int64_t kAdjoint4MinNodes = 1200000;
 
 // Kernel arguments in the compute real R.
 template <typename R>
@@ -139,6 +144,12 @@ hipError_t launch_adjoint_step(const KArgsAny& a, const void* prev, const void* 
 // mu_out.  Same result as two launch_adjoint_step calls.
 hipError_t launch_adjoint_step2(const KArgsAny& a, const void* prev_a, const void* prev_b, const void* mu_in,
                                 void* mu_out, void* grad_force, hipStream_t st);
+// Four adjoint steps in one launch (FP32): mu_in (cotangent of state n+1)
+// back through steps n, n-1, n-2, n-3 (states in prev_a .. prev_d) to mu_out.
+// Same result as four launch_adjoint_step calls.
+hipError_t launch_adjoint_step4(const KArgsAny& a, const void* prev_a, const void* prev_b, const void* prev_c,
+                                const void* prev_d, const void* mu_in, void* mu_out, void* grad_force,
+                                hipStream_t st);
 hipError_t launch_adjoint_macro(const KArgsAny& a, const void* lat, const void* g_rho, const void* g_ux,
                                 const void* g_uy, void* mu_out, void* grad_force, hipStream_t st);
 hipError_t launch_adjoint_init(const KArgsAny& a, const void* rho, const void* ux, const void* uy,

@@ -384,6 +384,37 @@ def test_adjoint_pairs_large_tiles(bci, shape):
     assert torch.equal(gf_a, gf_b)
 
 
+@pytest.mark.parametrize("n", [6, 9])
+@pytest.mark.parametrize("shape", [(1100, 1100), (1500, 1000), (20000, 70)])
+@pytest.mark.parametrize("bci", range(len(BCS)))
+def test_adjoint_quads(bci, shape, n):
+    """FP32 lattices of at least 1.2 M nodes run groups of four adjoint steps
+    as one launch (64 x 16 tiles, a four-node ring, three in-place stages in
+    LDS), then a pair or a single step: n = 6 is a quad and a pair, n = 9
+    two quads and a single step.  Ragged in x and y (1100 x 1100, 1500 x
+    1000) and a strip 20000 x 70.  Equal to n single adjoint steps,
+    grad_force included, bit for bit."""
+    (nx, ny) = shape
+    bc, wu = BCS[bci]
+    frc = W.force_field(nx, ny, 1e-4, seed=6)
+    lat = _lattice(nx, ny, frc, storage="fp32", tau=0.7, omega3=1.1, bc=bc, wall_u=wu)
+    lat.set_populations(W.random_populations(nx, ny, seed=8, amp=0.05))
+    src = lat.snapshot()
+    seq = [lat.new_lattice() for _ in range(n)]
+    lat.step_sequence(src, seq)
+    states = [src] + seq[:-1]
+    mu0 = _lattice_noise(lat, 3).to(lat.real)
+    gf_a = torch.from_numpy(W.force_field(nx, ny, 1.0, seed=7)).to(DEV, lat.real)
+    gf_b = gf_a.clone()
+    res = lat.adjoint_sequence(states, mu0.clone(), lat.new_cotangent(), gf_a)
+    mu, tmp = mu0.clone(), lat.new_cotangent()
+    for i in range(n - 1, -1, -1):
+        lat.adjoint_step(states[i], mu, tmp, gf_b)
+        mu, tmp = tmp, mu
+    assert torch.equal(res, mu)
+    assert torch.equal(gf_a, gf_b)
+
+
 def test_handle_on_another_stream():
     """Lattice.on_stream: a context of its own over the same buffers, whose
     calls run on the given stream.  Its kept states equal the original's; it
