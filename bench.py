@@ -410,44 +410,57 @@ def adjoint_rollout(n=512, T=2000, every=100):
             "grad_u0_rel_err_vs_fp64": float(f"{erru:.3e}")}
 
 
-def adjoint_pair_roofline(n=2048, pairs=50, copy_gbs=None):
-    """The adjoint pair launch (k_adjoint_step2, two adjoint steps) on an
+# Adjoint launches timed on their own: steps per launch -> (kernel,
+# algorithmic bytes per node and launch, counter summaries under profiles/).
+# Pair: two states 72, cotangent in 36 and out 36, force 8, force gradient
+# read and written 16.  Quad: four states 144 and the same 96 besides.
+ADJOINT_LAUNCHES = {
+    2: ("k_adjoint_step2<float> (two adjoint steps per launch)", 168,
+        "traffic_adjoint2_fp32_2048.txt", "valu_adjoint2_fp32_2048.txt"),
+    4: ("k_adjoint_step4<float> (four adjoint steps per launch)", 240,
+        "traffic_adjoint4_fp32_2048.txt", "valu_adjoint4_fp32_2048.txt"),
+}
+
+
+def adjoint_launch_roofline(n=2048, steps=2, launches=50, copy_gbs=None):
+    """One adjoint launch of `steps` steps (the pair k_adjoint_step2 or, on
+    lattices of 1.2 M nodes and more, the four-step k_adjoint_step4) on an
     n x n periodic FP32 lattice with a force field, timed with HIP events over
-    `pairs` launches: its HBM roofline at the algorithmic 168 B per node and
-    launch (two states 72, cotangent in 36 and out 36, force 8, force gradient
-    read and written 16)."""
+    `launches` launches: its HBM roofline at the algorithmic bytes per node
+    and launch."""
     import torch
     import workloads as W
     from paper_1202_6351_amd import Lattice, Params
+    kernel, bpn, f_traffic, f_valu = ADJOINT_LAUNCHES[steps]
     lat = Lattice(Params(n, n, tau=0.8, storage="fp32"), device="cuda:0",
                   force=torch.from_numpy(W.force_field(n, n, 1e-6, seed=4)))
     lat.init_equilibrium(*W.taylor_green(n, 0.02))
-    states = [lat.new_lattice() for _ in range(3)]
+    states = [lat.new_lattice() for _ in range(steps + 1)]
     lat.step_sequence(lat.snapshot(), states)
     mu_a, mu_b = lat.new_cotangent(), lat.new_cotangent()
     mu_a.normal_()
     gF = torch.zeros((2, n, n), dtype=torch.float32, device="cuda")
-    seq = [states[0], states[1]]
+    seq = states[:steps]
     lat.adjoint_sequence(seq, mu_a, mu_b, gF)  # warm-up
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(lat.stream)
-    for _ in range(pairs):
+    for _ in range(launches):
         lat.adjoint_sequence(seq, mu_a, mu_b, gF)
     e1.record(lat.stream)
     torch.cuda.synchronize()
-    per = e0.elapsed_time(e1) / 1e3 / pairs
-    alg = 168 * n * n / per / 1e9
-    traffic = counter_value("traffic_adjoint2_fp32_2048.txt", "traffic_bytes_per_launch") if n == 2048 else None
-    valu = counter_value("valu_adjoint2_fp32_2048.txt", "valu_wave_instructions_per_launch") if n == 2048 else None
-    out = {"kernel": "k_adjoint_step2<float> (two adjoint steps per launch)", "workload": f"adjoint_{n}x{n}_fp32",
-           "launch_us": round(per * 1e6, 2), "adjoint_glups": round(2 * n * n / per / 1e9, 2),
+    per = e0.elapsed_time(e1) / 1e3 / launches
+    alg = bpn * n * n / per / 1e9
+    traffic = counter_value(f_traffic, "traffic_bytes_per_launch") if n == 2048 else None
+    valu = counter_value(f_valu, "valu_wave_instructions_per_launch") if n == 2048 else None
+    out = {"kernel": kernel, "workload": f"adjoint_{n}x{n}_fp32",
+           "launch_us": round(per * 1e6, 2), "adjoint_glups": round(steps * n * n / per / 1e9, 2),
            "roofline": {"bound": "hbm", "achieved": round(alg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(alg / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
-                        "alg_bytes_per_node": 168,
+                        "alg_bytes_per_node": bpn,
                         "vs_copy": None if not copy_gbs else round(alg / copy_gbs, 4)}}
     if valu is not None:
-        out["valu_issue"] = {"lane_instructions_per_node_step": round(valu * 64 / (2 * n * n), 1),
+        out["valu_issue"] = {"lane_instructions_per_node_step": round(valu * 64 / (steps * n * n), 1),
                              "frac": round(valu * 64 / per / VALU_PEAK_OPS, 4)}
     return out
 
@@ -521,8 +534,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=4096, help="cavity size of the headline run")
-    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout", "rollout_keep_all", "rollout2048", "single"],
-                    default=None, help="time one storage mode, the forward + adjoint rollout, or the single-step "
+    ap.add_argument("--only", choices=["fp32", "fp16", "bf16", "fp64", "rollout", "rollout_keep_all", "rollout2048", "adjoint2048",
+                                       "single"],
+                    default=None, help="time one storage mode, the forward + adjoint rollout, the adjoint launches or the single-step "
                     "launches, only (profiling runs)")
     ap.add_argument("--rounding", choices=["nearest", "stochastic"], default="nearest",
                     help="16-bit rounding of an --only fp16/bf16 run")
@@ -553,6 +567,10 @@ def main():
         return
     if args.only == "single":
         print(json.dumps({"only": "single", **single_step_rates(copy_gbs=copy_bandwidth())}))
+        return
+    if args.only == "adjoint2048":
+        print(json.dumps({"only": "adjoint2048", "pair": adjoint_launch_roofline(2048, 2),
+                          "quad": adjoint_launch_roofline(2048, 4, launches=25)}))
         return
 
     if args.only in ("fp16", "bf16", "fp64"):
@@ -690,7 +708,8 @@ def main():
         # 18.9 GB): the backward runs the adjoint only, with no recompute
         forms["fwd_adjoint_keep_all"] = adjoint_rollout(512, 2000, 2000)
         forms["fwd_adjoint_2048"] = adjoint_rollout(2048, 400, 100)
-        forms["adjoint_pair_2048"] = adjoint_pair_roofline(2048, copy_gbs=copy_gbs)
+        forms["adjoint_pair_2048"] = adjoint_launch_roofline(2048, 2, copy_gbs=copy_gbs)
+        forms["adjoint_quad_2048"] = adjoint_launch_roofline(2048, 4, launches=25, copy_gbs=copy_gbs)
         line["forms"] = forms
     if args.only is None and not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, tau)
