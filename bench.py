@@ -424,7 +424,7 @@ ADJOINT_LAUNCHES = {
 
 def adjoint_launch_roofline(n=2048, steps=2, launches=50, copy_gbs=None):
     """One adjoint launch of `steps` steps (the pair k_adjoint_step2 or, on
-    lattices of 1.2 M nodes and more, the four-step k_adjoint_step4) on an
+    lattices of 200 000 nodes and more, the four-step k_adjoint_step4) on an
     n x n periodic FP32 lattice with a force field, timed with HIP events over
     `launches` launches: its HBM roofline at the algorithmic bytes per node
     and launch."""

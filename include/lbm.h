@@ -266,8 +266,8 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* lat_prev, const void* mu_i
  * lattice buffers of states k, k+1, ..., k+n-1 (host array of device
  * pointers), mu_a holds the cotangent of state k+n on entry.  The steps run
  * fused, the intermediate cotangents staying in on-chip memory: in groups
- * of four per launch on FP32 lattices of at least 1.2 M nodes (and at least
- * 128 x 64), then in pairs, an odd one alone; each launch ping-pongs
+ * of four per launch on FP32 lattices of at least 200 000 nodes (and at
+ * least 128 x 64), then in pairs, an odd one alone; each launch ping-pongs
  * between mu_a and mu_b (distinct buffers in lattice layout).  On return *result_in_b (host int)
  * is 0 if the cotangent of state k is in mu_a and 1 if it is in mu_b; the
  * other buffer is scratch.  grad_force as for lbm_adjoint_step (every step

@@ -1432,7 +1432,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_step2(KArgs<typename Codec<S>::R
 }
 
 // Four adjoint steps per launch (FP32 lattices of kAdjoint4MinNodes nodes or
-// more).  The window array holds the cotangents of a 64 x TY tile and a
+// more, 64 x TY tiles with TY = 8 or 16).  The window array holds the cotangents of a 64 x TY tile and a
 // four-node ring.  Stage 1 runs the adjoint of step n on the cells within
 // three nodes of the tile (mu_in from HBM) and scatters its reverse-streamed
 // result into the window, as the pair's first stage does.  Stages 2 and 3
@@ -1966,6 +1966,14 @@ hipError_t launch_adjoint_step4(const KArgsAny& a, const void* prev_a, const voi
                                 hipStream_t st) {
   const Geom& g = a.g();
   if (a.storage != 1) return hipErrorInvalidValue;
+  if ((int64_t)g.nx * g.ny <= kAdjoint2SmallMaxNodes) {
+    constexpr int TY = kAdjoint4TySmall, NT = kAdjoint4Threads;
+    const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
+    hipLaunchKernelGGL((k_adjoint_step4<float, TY, NT>), grid, dim3(NT), 0, st, a.f, (const float*)prev_a,
+                       (const float*)prev_b, (const float*)prev_c, (const float*)prev_d, (const float*)mu_in,
+                       (float*)mu_out, (float*)grad_force);
+    return hipGetLastError();
+  }
   constexpr int TY = kAdjoint4Ty, NT = kAdjoint4Threads;
   const dim3 grid((unsigned)(g.t2_tiles_x * ((g.ny + TY - 1) / TY)));
   hipLaunchKernelGGL((k_adjoint_step4<float, TY, NT>), grid, dim3(NT), 0, st, a.f, (const float*)prev_a,

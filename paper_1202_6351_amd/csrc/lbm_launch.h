@@ -75,9 +75,13 @@ constexpr int kAdjoint2TyF32Small = 8, kAdjoint2ThreadsF32Small = 512;
 constexpr int64_t kAdjoint2SmallMaxNodes = 600000;
 // Four-step adjoint (FP32 only): 64 x TY tiles, NT threads, used for groups
 // of four steps on lattices of at least kAdjoint4MinNodes nodes that are at
-// least 128 x 64 (below that the pairs' shorter latency chain wins).
-constexpr int kAdjoint4Ty = 16, kAdjoint4Threads = 512;
-constexpr int64_t kAdjoint4MinNodes = 1200000;
+// least 128 x 64; 64 x 8 tiles up to kAdjoint2SmallMaxNodes nodes, 64 x 16
+// above.  Measured against pairs: 2048^2, 296.5 us per launch against two
+// pair launches of 167.8 us; 512^2 (64 x 8), the FP32 rollout (T = 2000,
+// checkpoint 100) 24.0 -> 22.4 ms.  Smaller lattices keep the pairs, whose
+// latency chain is shorter (not measured below 512^2).
+constexpr int kAdjoint4Ty = 16, kAdjoint4TySmall = 8, kAdjoint4Threads = 512;
+constexpr int64_t kAdjoint4MinNodes = 200000;
 
 // Kernel arguments in the compute real R.
 template <typename R>

@@ -360,10 +360,12 @@ def test_sequences_equal_single_calls(storage, n, bci, shape):
 def test_adjoint_pairs_large_tiles(bci, shape):
     """FP32 adjoint pairs on 64 x 8 tiles, with 256 threads on lattices above
     600 000 nodes (801 x 800, ragged in x) and 512 threads below (512 x 512,
-    the rollout benchmark's launch; 700 x 511, ragged in x and y): five
-    steps (two pairs and a single step) equal five single adjoint steps,
+    the rollout benchmark's launch; 700 x 511, ragged in x and y).  These
+    lattices run groups of four steps as one four-step launch (64 x 16 tiles
+    above 600 000 nodes, 64 x 8 below), so seven steps are a four-step
+    launch, a pair and a single step: equal to seven single adjoint steps,
     grad_force included, bit for bit."""
-    (nx, ny), n = shape, 5
+    (nx, ny), n = shape, 7
     bc, wu = BCS[bci]
     frc = W.force_field(nx, ny, 1e-4, seed=6)
     lat = _lattice(nx, ny, frc, storage="fp32", tau=0.7, omega3=1.1, bc=bc, wall_u=wu)
@@ -385,15 +387,16 @@ def test_adjoint_pairs_large_tiles(bci, shape):
 
 
 @pytest.mark.parametrize("n", [6, 9])
-@pytest.mark.parametrize("shape", [(1100, 1100), (1500, 1000), (20000, 70)])
+@pytest.mark.parametrize("shape", [(1100, 1100), (1500, 1000), (20000, 70), (700, 511), (4000, 64)])
 @pytest.mark.parametrize("bci", range(len(BCS)))
 def test_adjoint_quads(bci, shape, n):
-    """FP32 lattices of at least 1.2 M nodes run groups of four adjoint steps
-    as one launch (64 x 16 tiles, a four-node ring, three in-place stages in
-    LDS), then a pair or a single step: n = 6 is a quad and a pair, n = 9
-    two quads and a single step.  Ragged in x and y (1100 x 1100, 1500 x
-    1000) and a strip 20000 x 70.  Equal to n single adjoint steps,
-    grad_force included, bit for bit."""
+    """FP32 lattices of at least 200 000 nodes (and at least 128 x 64) run
+    groups of four adjoint steps as one launch (a four-node ring, three
+    in-place stages in LDS), then a pair or a single step: n = 6 is a quad
+    and a pair, n = 9 two quads and a single step.  64 x 16 tiles above
+    600 000 nodes: ragged in x and y (1100 x 1100, 1500 x 1000) and a strip
+    20000 x 70; 64 x 8 tiles below: 700 x 511 and a strip 4000 x 64.  Equal
+    to n single adjoint steps, grad_force included, bit for bit."""
     (nx, ny) = shape
     bc, wu = BCS[bci]
     frc = W.force_field(nx, ny, 1e-4, seed=6)
