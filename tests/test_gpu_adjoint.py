@@ -296,11 +296,13 @@ def test_rollout_matches_torch_autograd(bci, case):
     assert eF <= tol and eu <= tol
 
 
-def test_rollout_fp32_gradient_close_to_fp64():
-    """The FP32 adjoint agrees with the FP64 one to FP32 accuracy (64x64,
-    T = 300, checkpoint every 100)."""
+@pytest.mark.parametrize("n,T", [(64, 300), (512, 60)])
+def test_rollout_fp32_gradient_close_to_fp64(n, T):
+    """The FP32 adjoint agrees with the FP64 one to FP32 accuracy (checkpoint
+    every 100; at 512 x 512 the FP32 adjoint runs four steps per launch, the
+    FP64 one pairs, so the two launch forms are tied together)."""
     from paper_1202_6351_amd import Params, rollout
-    n, tau, T = 64, 0.8, 300
+    tau = 0.8
     target = _tg_target(n, T, tau)
     grads = {}
     for storage in ("fp64", "fp32"):
