@@ -719,8 +719,12 @@ __device__ __forceinline__ void core_force(const KArgs<R>& a, int gx, int gy, R&
 // cells go in batches of B: the loads of a whole batch are issued before its
 // first collision.  FW: also keep each cell's force in fw ([2][EH][EW]) for
 // the later stages.  KEEP: also store the result of the tile's nodes to keep.
+// PRIO: the waves issue a batch's loads at raised priority, so that on a SIMD
+// they go out ahead of another workgroup's arithmetic (four-step launches:
+// FP32 cavity 4096^2, 284.7 -> 280.0 us per launch, A/B twice on one box;
+// the two-step 16-bit launch got 2.5 % slower with it and does without).
 template <typename S, int FM, bool SR, int EH, int EW, int NT, bool U, int B, bool FW = false, bool KEEP = false,
-          int EHP>
+          bool PRIO = false, int EHP>
 __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>& a,
                                                const Rates<typename Codec<S>::R>& rt, const S* __restrict__ src,
                                                int wx0, int wy0, uint32_t key, S (&mid)[9][EHP][EW],
@@ -739,6 +743,7 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
   for (int j0 = 0; j0 < NPT; j0 += B) {
     R d[B][9];
     uint32_t off[B];
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int jb = 0; jb < B; ++jb) {
       const int j = j0 + jb, i = t + NT * j;
@@ -749,6 +754,7 @@ __device__ __forceinline__ void core_stage_hbm(const KArgs<typename Codec<S>::R>
         for (int k = 0; k < 9; ++k) d[jb][k] = Codec<S>::load(BufIO<S>::load(rs, off[jb], g.ld_soff[k]));
       }
     }
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int jb = 0; jb < B; ++jb) {
       const int j = j0 + jb, i = t + NT * j;
@@ -1067,7 +1073,8 @@ __global__ __launch_bounds__(NT) void k_step4(KArgs<typename Codec<S>::R> a, con
     if (fast) {  // workgroup-uniform: an interior tile of a lattice below 4 GiB
       // (a force field is read at the cells' own, unwrapped nodes: in every
       // stage, or once into fw)
-      core_stage_hbm<S, FM, SR, EH, EW, NT, U, 3, FW, KEEP>(a, rt, src, x0 - H, y0 - H, key_a, mid, fw, keep0);
+      core_stage_hbm<S, FM, SR, EH, EW, NT, U, 3, FW, KEEP, true>(a, rt, src, x0 - H, y0 - H, key_a, mid, fw,
+                                                                  keep0);
       __syncthreads();
       core_stage_lds<S, FM, SR, EH, EW, H, 2, NT, U, FW, KEEP>(a, rt, x0 - H, y0 - H, key_b, mid, fw, keep1);
       if (KEEP && !keep2) return;
